@@ -1,0 +1,199 @@
+/*
+ * mr.h -- C ABI of the multiresolution block-octree hot path on one MI355X.
+ *
+ * Method: Gillis & van Rees, "MURPHY -- a scalable multiresolution framework
+ * for scientific computing on 3D block-structured collocated grids"
+ * (arXiv 2112.07537).  A periodic unit cube is covered by a 2:1-balanced
+ * octree of cubic blocks of nb^3 points; a scalar phi obeys
+ * d(phi)/dt + div(u phi) = 0 (transport problem of section 5, divergence-free
+ * u).  Ghost points across resolution jumps, block refinement / coarsening and
+ * the refinement criterion all use interpolating wavelets N.Nt with
+ * N in {2,4,6}, Nt in {0,2} (section 2, filter tables of the supplementary
+ * filter-bank section).
+ *
+ * Conventions
+ *  - Every call returns an mr_status; MR_OK is 0, errors are negative.  On an
+ *    error, mr_last_error() returns a thread-local message.  Invalid
+ *    arguments give MR_EINVAL and change no state.
+ *  - Geometry: block (L, i, j, k) has spacing h_L = 2^-L / nb; its local point
+ *    (x, y, z) sits at ((i*nb + x), (j*nb + y), (k*nb + z)) * h_L (node-based,
+ *    left-aligned).  Field data are block-major: block b occupies nb^3
+ *    consecutive values with x fastest, then y, then z.  Blocks are ordered
+ *    by Morton key of (L, i, j, k); the order changes at every adaptation.
+ *  - Precision: bulk arrays are FP64 (MR_F64) or FP32 (MR_F32); the detail
+ *    transform, its norms, threshold comparisons and moment sums are FP64.
+ *  - Host pointers passed in are caller-owned and only read/written during
+ *    the call.  Device memory is owned by the library (hipMalloc) and freed
+ *    by mr_grid_destroy.
+ *  - Streams: device work is issued on the hipStream_t given at creation
+ *    (NULL = default stream).  mr_ghost, mr_rk3_step and mr_details with
+ *    on_device = 1 are asynchronous; every other call synchronises the stream.
+ *  - A grid handle is not thread-safe.
+ */
+#ifndef MR_H
+#define MR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mr_grid mr_grid; /* opaque, owned by the library */
+
+typedef enum {
+  MR_OK = 0,
+  MR_EINVAL = -1,     /* invalid argument or configuration                */
+  MR_ENOMEM = -2,     /* device or host allocation failed                 */
+  MR_ECAPACITY = -3,  /* block capacity (max_blocks) would be exceeded    */
+  MR_EHIP = -4,       /* a HIP runtime call failed                        */
+  MR_ESTATE = -5,     /* call not valid in the grid's current state       */
+  MR_ENONFINITE = -6  /* a detail norm came out NaN or infinite           */
+} mr_status;
+
+typedef enum { MR_F64 = 0, MR_F32 = 1 } mr_prec;
+
+/* Grid configuration (section 2.2 and the adaptation supplement). */
+typedef struct {
+  int32_t nb;          /* points per block edge: 8, 16 or 24               */
+  int32_t wavelet_N;   /* interpolation order N: 2, 4 or 6                  */
+  int32_t wavelet_Nt;  /* vanishing moments Nt: 0 (Donoho) or 2 (lifted)    */
+  int32_t fd_order;    /* central first-derivative order: 4 or 6            */
+  int32_t level_min;   /* 0 <= level_min <= level_max <= 12                 */
+  int32_t level_max;
+  int32_t prec;        /* mr_prec of field arrays                           */
+  int32_t detail_ext;  /* 1: criterion includes the extension band of the
+                          "coarse region extension" column of Table 3 taken
+                          in same-level neighbours; 0: block interior only  */
+  int32_t n_fields;    /* scalar fields carried by the grid (>= 1)          */
+  int32_t exec_mode;   /* 0: batched launches (default); 1: plain, one
+                          launch per block per operation; 2: batched with
+                          the whole RK3 step captured in a hipGraph         */
+  double eps_refine;   /* refine if ||gamma||_inf >= eps_refine (absolute)  */
+  double eps_coarsen;  /* coarsen if all 8 siblings <= eps_coarsen          */
+  int64_t max_blocks;  /* capacity of the block pool                        */
+} mr_config;
+
+/* Velocity fields; each component does not depend on its own coordinate,
+ * so the advective and conservative forms coincide. */
+enum { MR_VEL_CONST = 0,    /* u = (p0, p1, p2)                             */
+       MR_VEL_ROTATING = 1, /* u = (-(y - p1), x - p0, p2)                  */
+       MR_VEL_SHEAR = 2 };  /* u = (sin 2pi z, sin 2pi x, sin 2pi y)        */
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  double p[8];
+} mr_velocity;
+
+/* Analytic initial conditions (evaluated in FP64). */
+enum { MR_IC_GAUSS_SUM = 0,  /* n terms, params[5*g..5*g+4] = cx, cy, cz,
+                                sigma, a: a*exp(-|x-c|^2/sigma^2) with the
+                                minimum-image periodic distance              */
+       MR_IC_TANH_SHELL = 1 }; /* params = ax, ay, az, w:
+                                0.5*(1 - tanh(d/w)), d = (rho-1)*min(a),
+                                rho = |(x - 1/2)/a| (component-wise)         */
+typedef struct {
+  int32_t kind;
+  int32_t n;
+  const double* params;
+} mr_ic;
+
+typedef struct {
+  int32_t iters;      /* adaptation iterations that changed the tree     */
+  int32_t refined;    /* blocks refined (each into 8)                     */
+  int32_t coarsened;  /* sibling sets coarsened (each 8 into 1)           */
+  int32_t in_band;    /* blocks whose norm is within 1e-4 relative of a
+                         threshold at the last flag evaluation            */
+  int64_t n_blocks;   /* leaves after adaptation                          */
+} mr_adapt_stats;
+
+/* Create a grid.  hip_stream: a hipStream_t or NULL.  The tree starts as the
+ * uniform tree at level_min with zero fields.  Warns (mr_last_error) but
+ * succeeds when eps_refine/eps_coarsen <= 2^N (section 2.2.5: flip-flops). */
+mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, mr_grid** out);
+mr_status mr_grid_destroy(mr_grid* g);
+
+/* Replace the tree by the n leaves (level[i], ijk[3*i..3*i+2]); the set must
+ * tile the unit cube and be 2:1 balanced over the 26-neighbourhood with the
+ * periodic wrap, else MR_EINVAL.  Fields are set to zero. */
+mr_status mr_set_tree(mr_grid* g, int64_t n, const int32_t* level, const int32_t* ijk);
+
+/* Evaluate the initial condition on every current leaf of field `field`. */
+mr_status mr_sample_ic(mr_grid* g, int32_t field, const mr_ic* ic);
+
+/* Initial grid: uniform at level_min, then {sample the IC, criterion,
+ * refine only} until stable, then one adaptation (mr_adapt).  */
+mr_status mr_init_ic(mr_grid* g, int32_t field, const mr_ic* ic, int32_t max_iter,
+                     mr_adapt_stats* stats);
+
+/* Ghost reconstruction of `field` (sections 2.2.2, 2.2.4 and the ghosting
+ * algorithms Part 1 / Part 2): substitution on fine blocks next to coarser
+ * leaves, then ghost patches of `depth` points (0 = stencil depth
+ * fd_order/2) across every resolution jump.  Asynchronous. */
+mr_status mr_ghost(mr_grid* g, int32_t field, int32_t depth);
+
+/* Copy blocks [b0, b0+nblk) of `field` with their ghost layer of `depth`
+ * points, as filled by the last mr_ghost of that depth, to host memory:
+ * (nb+2*depth)^3 values per block in field precision.  Synchronises. */
+mr_status mr_ghost_get(mr_grid* g, int32_t field, int32_t depth, int64_t b0,
+                       int64_t nblk, void* host, size_t bytes);
+
+/* Block criterion of section 2.2.5: ghost reconstruction, one-level forward
+ * transform (x, y, z), per-block max |gamma| (FP64).  norms: n_blocks
+ * doubles, host (on_device = 0, synchronises) or device (on_device = 1). */
+mr_status mr_details(mr_grid* g, int32_t field, double* norms, int32_t on_device);
+
+/* Iterative adaptation (adaptation supplement): criterion, flags, policy
+ * (refinement priority and propagation, 2:1, no coarsening of blocks refined
+ * in this call, level bounds), refine / coarsen all fields, update step, until
+ * no block changes or max_iter iterations.  An iteration whose new tree would
+ * exceed max_blocks is not applied (MR_ECAPACITY); iterations already applied
+ * in the same call remain.  Synchronises. */
+mr_status mr_adapt(mr_grid* g, int32_t field, int32_t max_iter, mr_adapt_stats* stats);
+
+/* One SSP-RK3 step of `field` (time-integration supplement) with central FD
+ * advection; each stage reconstructs the ghosts first.  Asynchronous. */
+mr_status mr_rk3_step(mr_grid* g, int32_t field, double dt, const mr_velocity* vel);
+
+/* dt = cfl * h_min / max_x sum_d |u_d(x)| for the current tree. */
+mr_status mr_cfl_dt(const mr_grid* g, const mr_velocity* vel, double cfl, double* dt);
+
+/* Leaf metadata in block order: *n receives the leaf count; level and ijk
+ * (3 per leaf) are written when non-NULL and must hold *n_cap entries. */
+mr_status mr_block_meta(const mr_grid* g, int64_t n_cap, int64_t* n, int32_t* level,
+                        int32_t* ijk);
+
+/* Copy the field to/from host memory, block-major, field precision.
+ * bytes must equal n_blocks*nb^3*sizeof(value).  Synchronises. */
+mr_status mr_field_get(mr_grid* g, int32_t field, void* host, size_t bytes);
+mr_status mr_field_set(mr_grid* g, int32_t field, const void* host, size_t bytes);
+
+/* Device pointer of a field (valid until the next mr_adapt / mr_set_tree /
+ * mr_init_ic / mr_grid_destroy). */
+mr_status mr_field_ptr(mr_grid* g, int32_t field, void** dev_ptr);
+
+/* FP64 discrete moments (section 2.1.4, per axis): out[0] = sum h^3 phi,
+ * out[1..3] = sum h^3 phi x_d.  Synchronises. */
+mr_status mr_moments(mr_grid* g, int32_t field, double out[4]);
+
+/* Kernel timing with HIP events recorded on the grid's stream around each
+ * launch of the named kernel family ("rhs", "details", "ghost_refine",
+ * "ghost_restrict").  mr_prof_enable(g, 1) clears and starts recording;
+ * mr_prof_read synchronises and returns the summed milliseconds, the number
+ * of launches and the points processed per launch. */
+mr_status mr_prof_enable(mr_grid* g, int32_t on);
+mr_status mr_prof_read(mr_grid* g, const char* kernel, double* total_ms, int64_t* launches,
+                       int64_t* points_per_launch);
+
+/* Counts describing the current tree: out[0] = leaves, out[1] = cross-level
+ * ghost patch values at stencil depth, out[2] = substituted-slab work items,
+ * out[3] = finest level present, out[4] = coarsest level present. */
+mr_status mr_tree_stats(const mr_grid* g, int64_t out[5]);
+
+const char* mr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MR_H */

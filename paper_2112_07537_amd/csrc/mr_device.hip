@@ -1,0 +1,1093 @@
+// HIP kernels (gfx950) of the multiresolution block-octree hot path.
+//
+// Method: Gillis & van Rees, MURPHY (arXiv 2112.07537).  Filter constants are
+// those of the supplementary filter-bank tables (non-lifted 2.0/4.0/6.0 and
+// lifted 2.2/4.2/6.2, acting on interleaved scaling/detail coefficients).
+// Everything here is short stencil or filter work on blocks, so it is written
+// for the memory system (coalesced block rows, LDS planes, register columns),
+// not for the matrix cores.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "mr_internal.h"
+
+namespace mr {
+
+// ------------------------------------------------------------------ filters
+// Deslauriers-Dubuc prediction of order N (K^s at the scaling positions):
+// odd fine value 2k+1 = sum_j w[j - J0] * lambda_{k+j}, j in [1-N/2, N/2].
+template <int N> struct DD;
+template <> struct DD<2> {
+  static constexpr int J0 = 0;
+  __device__ static constexpr double w(int i) { return 0.5; }
+};
+template <> struct DD<4> {
+  static constexpr int J0 = -1;
+  __device__ static constexpr double w(int i) {
+    return (i == 0 || i == 3) ? -1.0 / 16.0 : 9.0 / 16.0;
+  }
+};
+template <> struct DD<6> {
+  static constexpr int J0 = -2;
+  __device__ static constexpr double w(int i) {
+    return (i == 0 || i == 5) ? 3.0 / 256.0 : ((i == 1 || i == 4) ? -25.0 / 256.0 : 75.0 / 128.0);
+  }
+};
+
+// Analysis H^a (even positions), reach HR, and G^a (odd positions), reach N-1.
+template <int N, int NT> struct Ha;
+template <int N> struct Ha<N, 0> {
+  static constexpr int R = 0;
+  __device__ static constexpr double c(int o) { return o == 0 ? 1.0 : 0.0; }
+};
+template <> struct Ha<2, 2> {
+  static constexpr int R = 2;
+  __device__ static constexpr double c(int o) {
+    return o == 0 ? 0.75 : ((o == 1 || o == -1) ? 0.25 : -0.125);
+  }
+};
+template <> struct Ha<4, 2> {
+  static constexpr int R = 4;
+  __device__ static constexpr double c(int o) {
+    return o == 0 ? 23.0 / 32.0
+         : (o == 1 || o == -1) ? 0.25
+         : (o == 2 || o == -2) ? -0.125
+         : (o == 4 || o == -4) ? 1.0 / 64.0 : 0.0;
+  }
+};
+template <> struct Ha<6, 2> {
+  static constexpr int R = 6;
+  __device__ static constexpr double c(int o) {
+    return o == 0 ? 181.0 / 256.0
+         : (o == 1 || o == -1) ? 0.25
+         : (o == 2 || o == -2) ? -125.0 / 1024.0
+         : (o == 4 || o == -4) ? 11.0 / 512.0
+         : (o == 6 || o == -6) ? -3.0 / 1024.0 : 0.0;
+  }
+};
+template <int N> struct Ga {
+  static constexpr int R = N - 1;
+  // centre 1, odd offsets minus the DD weights, even offsets 0
+  __device__ static constexpr double c(int o) {
+    return o == 0 ? 1.0 : ((o & 1) ? -DD<N>::w((o + 1) / 2 - DD<N>::J0) : 0.0);
+  }
+};
+// Synthesis J^s (even) and K^s (odd) of the interleaved layout.
+template <int N, int NT> struct Js;
+template <int N> struct Js<N, 0> {
+  static constexpr int R = 0;
+  __device__ static constexpr double c(int o) { return o == 0 ? 1.0 : 0.0; }
+};
+template <int N> struct Js<N, 2> {
+  static constexpr int R = 1;
+  __device__ static constexpr double c(int o) { return o == 0 ? 1.0 : -0.25; }
+};
+template <int N, int NT> struct Ks;
+template <int N> struct Ks<N, 0> {
+  static constexpr int R = N - 1;
+  __device__ static constexpr double c(int o) {
+    return o == 0 ? 1.0 : ((o & 1) ? DD<N>::w((o + 1) / 2 - DD<N>::J0) : 0.0);
+  }
+};
+template <int N> struct Ks<N, 2> {
+  static constexpr int R = N;
+  // odd offsets: DD weights; even offsets: -1/4 * (DD-weighted J^s neighbours)
+  __device__ static constexpr double c(int o) {
+    if (o & 1) return DD<N>::w((o + 1) / 2 - DD<N>::J0);
+    // f[2k+1] gets -1/4 (gamma_{k-1+j} + gamma_{k+j}) through each lambda_{k+j}
+    // used by the prediction; collect the weight of gamma at offset o.
+    double s = (o == 0) ? 1.0 : 0.0;
+    for (int i = 0; i < N; ++i) {
+      int j = i + DD<N>::J0;           // lambda_{k+j} at offset 2j-1
+      int lo = 2 * j - 2, hi = 2 * j;  // gammas around it at offsets 2j-2, 2j
+      if (o == lo || o == hi) s += -0.25 * DD<N>::w(i);
+    }
+    return s;
+  }
+};
+
+// ------------------------------------------------------------ index helpers
+__device__ __forceinline__ int floordiv(int a, int b) {
+  int q = a / b;
+  return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+__device__ __forceinline__ int wrapi(int a, int w) {
+  int r = a % w;
+  return r < 0 ? r + w : r;
+}
+
+// Leaf id holding the level-(L+up) point q given relative to block m.
+template <typename T>
+__device__ __forceinline__ int owner_id(const DevGrid<T>& g, int m, int up, int qx, int qy, int qz) {
+  const int h = g.nb >> 1;
+  int cx = ((qx >> up) + h) / h, cy = ((qy >> up) + h) / h, cz = ((qz >> up) + h) / h;
+  if ((unsigned)cx > 3u || (unsigned)cy > 3u || (unsigned)cz > 3u) {
+    atomicAdd(g.err, 1);
+    return -1;
+  }
+  return g.cmap[m * 64 + (cz * 4 + cy) * 4 + cx];
+}
+
+// Value of leaf `id` at the level-Lq point with global coordinates Q (wrapped
+// here); requires Q on the leaf's grid.  Returns false if it is not.
+template <typename T>
+__device__ __forceinline__ bool leaf_value(const DevGrid<T>& g, int id, int Lq, int Qx, int Qy,
+                                           int Qz, T& v) {
+  const int nb = g.nb;
+  const int W = nb << Lq;
+  Qx = wrapi(Qx, W);
+  Qy = wrapi(Qy, W);
+  Qz = wrapi(Qz, W);
+  const int l = g.lev[id];
+  int lx, ly, lz;
+  if (l >= Lq) {
+    int s = l - Lq;
+    lx = (Qx << s) - g.ijk[3 * id] * nb;
+    ly = (Qy << s) - g.ijk[3 * id + 1] * nb;
+    lz = (Qz << s) - g.ijk[3 * id + 2] * nb;
+  } else {
+    int s = Lq - l, msk = (1 << s) - 1;
+    if ((Qx & msk) | (Qy & msk) | (Qz & msk)) return false;
+    lx = (Qx >> s) - g.ijk[3 * id] * nb;
+    ly = (Qy >> s) - g.ijk[3 * id + 1] * nb;
+    lz = (Qz >> s) - g.ijk[3 * id + 2] * nb;
+  }
+  if ((unsigned)lx >= (unsigned)nb || (unsigned)ly >= (unsigned)nb || (unsigned)lz >= (unsigned)nb) {
+    atomicAdd(g.err, 1);
+    return false;
+  }
+  v = g.field[(int64_t)id * nb * nb * nb + ((int64_t)lz * nb + ly) * nb + lx];
+  return true;
+}
+
+// Value of block b's level-L field extended by its ghost layer: own points,
+// same-level neighbours, or the cross-level patch of the region.
+template <typename T>
+__device__ __forceinline__ T ext_value(const DevGrid<T>& g, int b, int x, int y, int z) {
+  const int nb = g.nb;
+  const int rx = x < 0 ? 0 : (x < nb ? 1 : 2);
+  const int ry = y < 0 ? 0 : (y < nb ? 1 : 2);
+  const int rz = z < 0 ? 0 : (z < nb ? 1 : 2);
+  const int r = rx + 3 * ry + 9 * rz;
+  const int64_t nb3 = (int64_t)nb * nb * nb;
+  if (r == 13) return g.field[b * nb3 + ((int64_t)z * nb + y) * nb + x];
+  const int64_t po = g.poff[(int64_t)b * 27 + r];
+  if (po < 0) {
+    const int cx = rx == 0 ? 0 : (rx == 1 ? 1 : 3);
+    const int cy = ry == 0 ? 0 : (ry == 1 ? 1 : 3);
+    const int cz = rz == 0 ? 0 : (rz == 1 ? 1 : 3);
+    const int n = g.cmap[b * 64 + (cz * 4 + cy) * 4 + cx];
+    return g.field[n * nb3 + ((int64_t)(z - (rz - 1) * nb) * nb + (y - (ry - 1) * nb)) * nb +
+                   (x - (rx - 1) * nb)];
+  }
+  const int dw = g.dw;
+  const int sx = rx == 1 ? nb : dw, sy = ry == 1 ? nb : dw;
+  const int lx = rx == 0 ? -dw : (rx == 1 ? 0 : nb);
+  const int ly = ry == 0 ? -dw : (ry == 1 ? 0 : nb);
+  const int lz = rz == 0 ? -dw : (rz == 1 ? 0 : nb);
+  return g.patch[po + ((int64_t)(z - lz) * sy + (y - ly)) * sx + (x - lx)];
+}
+
+// ------------------------------------------------- zero-detail refinement
+// One workgroup per GItem.  LDS: coarse samples S, x-refined T1, y-refined T2.
+template <typename T, int N>
+__device__ __forceinline__ T refine_tap(const T* line, int stride, int p, int c0) {
+  // fine position p from coarse samples line[(c - c0)*stride]
+  if ((p & 1) == 0) return line[(floordiv(p, 2) - c0) * stride];
+  const int k = floordiv(p - 1, 2);
+  T acc = T(0);
+#pragma unroll
+  for (int i = 0; i < N; ++i) acc += T(DD<N>::w(i)) * line[(k + i + DD<N>::J0 - c0) * stride];
+  return acc;
+}
+
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(256) void k_gview(DevGrid<T> g, const GItem* __restrict__ items) {
+  extern __shared__ unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  const GItem it = items[blockIdx.x];
+  const int m = it.blk;
+  const int L = g.lev[m];
+  int clo[3], cs[3], fs[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    clo[a] = floordiv(it.lo[a], 2) - N / 2;
+    cs[a] = floordiv(it.hi[a] - 1, 2) + N / 2 + 1 - clo[a];
+    fs[a] = it.hi[a] - it.lo[a];
+  }
+  T* S = lds;                              // [cs2][cs1][cs0]
+  T* T1 = S + cs[0] * cs[1] * cs[2];       // [cs2][cs1][fs0]
+  T* T2 = T1 + fs[0] * cs[1] * cs[2];      // [cs2][fs1][fs0]
+  const int nb = g.nb;
+  const int ox = g.ijk[3 * m] * nb, oy = g.ijk[3 * m + 1] * nb, oz = g.ijk[3 * m + 2] * nb;
+  // samples at level L + up - 1, i.e. level-L points p = c << (1 - up)
+  const int sh = 1 - it.up;
+  const int ns = cs[0] * cs[1] * cs[2];
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    const int cx = clo[0] + i % cs[0];
+    const int cy = clo[1] + (i / cs[0]) % cs[1];
+    const int cz = clo[2] + i / (cs[0] * cs[1]);
+    const int px = cx << sh, py = cy << sh, pz = cz << sh;
+    T v = T(0);
+    const int id = owner_id(g, m, 0, px, py, pz);
+    if (id >= 0 && !leaf_value(g, id, L, ox + px, oy + py, oz + pz, v)) atomicAdd(g.err, 1);
+    S[i] = v;
+  }
+  __syncthreads();
+  const int n1 = fs[0] * cs[1] * cs[2];
+  for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+    const int fx = i % fs[0];
+    const int r = i / fs[0];   // (cz, cy) row
+    T1[i] = refine_tap<T, N>(S + r * cs[0], 1, it.lo[0] + fx, clo[0]);
+  }
+  __syncthreads();
+  const int n2 = fs[0] * fs[1] * cs[2];
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+    const int fx = i % fs[0];
+    const int fy = (i / fs[0]) % fs[1];
+    const int cz = i / (fs[0] * fs[1]);
+    T2[i] = refine_tap<T, N>(T1 + cz * fs[0] * cs[1] + fx, fs[0], it.lo[1] + fy, clo[1]);
+  }
+  __syncthreads();
+  const int n3 = fs[0] * fs[1] * fs[2];
+  const int64_t nb3 = (int64_t)nb * nb * nb;
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) {
+    const int fx = i % fs[0];
+    const int fy = (i / fs[0]) % fs[1];
+    const int fz = i / (fs[0] * fs[1]);
+    const T v = refine_tap<T, N>(T2 + fy * fs[0] + fx, fs[0] * fs[1], it.lo[2] + fz, clo[2]);
+    const int x = it.lo[0] + fx, y = it.lo[1] + fy, z = it.lo[2] + fz;
+    if (it.mode == 0) {
+      const int par[3] = {x & 1, y & 1, z & 1};
+      bool take;
+      if (it.sel & 8) {
+        take = (par[0] | par[1] | par[2]) != 0;
+      } else {
+        take = true;
+        bool tang_odd = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          if (it.sel & (1 << a)) take = take && (par[a] == 0);
+          else tang_odd = tang_odd || (par[a] == 1);
+        }
+        take = take && tang_odd;
+      }
+      if (take) g.field[m * nb3 + ((int64_t)z * nb + y) * nb + x] = v;
+    } else {
+      T* out = it.buf ? g.scratch : g.patch;
+      out[it.off + ((int64_t)(z - it.rlo[2]) * it.rsz[1] + (y - it.rlo[1])) * it.rsz[0] +
+          (x - it.rlo[0])] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------ restriction (f->c)
+template <typename T, int N, int NT>
+__device__ __forceinline__ T fine_view(const DevGrid<T>& g, const RItem& it, int L, int ox, int oy,
+                                       int oz, int px, int py, int pz) {
+  // level-(L+1) point p relative to 2*origin(C)
+  const int id = owner_id(g, it.blk, 1, px, py, pz);
+  T v = T(0);
+  if (id < 0) return v;
+  if (g.lev[id] == L + 1) {
+    leaf_value(g, id, L + 1, 2 * ox + px, 2 * oy + py, 2 * oz + pz, v);
+    return v;
+  }
+  if (g.lev[id] > L + 1) {  // finer still: injection (never produced by the owner map)
+    leaf_value(g, id, L + 1, 2 * ox + px, 2 * oy + py, 2 * oz + pz, v);
+    return v;
+  }
+  const int gx = px - it.glo[0], gy = py - it.glo[1], gz = pz - it.glo[2];
+  if ((unsigned)gx >= (unsigned)it.gsz[0] || (unsigned)gy >= (unsigned)it.gsz[1] ||
+      (unsigned)gz >= (unsigned)it.gsz[2]) {
+    atomicAdd(g.err, 1);
+    return v;
+  }
+  return g.scratch[it.goff + ((int64_t)gz * it.gsz[1] + gy) * it.gsz[0] + gx];
+}
+
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(256) void k_rview(DevGrid<T> g, const RItem* __restrict__ items) {
+  extern __shared__ unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  const RItem it = items[blockIdx.x];
+  const int m = it.blk;
+  const int L = g.lev[m];
+  const int nb = g.nb;
+  const int ox = g.ijk[3 * m] * nb, oy = g.ijk[3 * m + 1] * nb, oz = g.ijk[3 * m + 2] * nb;
+  constexpr int H = Ha<N, NT>::R;
+  int qs[3], flo[3], fsz[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    qs[a] = it.hi[a] - it.lo[a];
+    flo[a] = 2 * it.lo[a] - H;
+    fsz[a] = 2 * (qs[a] - 1) + 1 + 2 * H;
+  }
+  T* R1 = lds;                              // [fz][fy][qx]
+  T* R2 = R1 + qs[0] * fsz[1] * fsz[2];     // [fz][qy][qx]
+  const int n1 = qs[0] * fsz[1] * fsz[2];
+  for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+    const int qx = i % qs[0];
+    const int fy = (i / qs[0]) % fsz[1];
+    const int fz = i / (qs[0] * fsz[1]);
+    const int px = 2 * (it.lo[0] + qx), py = flo[1] + fy, pz = flo[2] + fz;
+    T acc = T(0);
+#pragma unroll
+    for (int o = -H; o <= H; ++o) {
+      if (Ha<N, NT>::c(o) != 0.0)
+        acc += T(Ha<N, NT>::c(o)) * fine_view<T, N, NT>(g, it, L, ox, oy, oz, px + o, py, pz);
+    }
+    R1[i] = acc;
+  }
+  __syncthreads();
+  const int n2 = qs[0] * qs[1] * fsz[2];
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+    const int qx = i % qs[0];
+    const int qy = (i / qs[0]) % qs[1];
+    const int fz = i / (qs[0] * qs[1]);
+    const int c = 2 * qy + H;  // window index of fine 2*(lo+qy)
+    T acc = T(0);
+#pragma unroll
+    for (int o = -H; o <= H; ++o) {
+      if (Ha<N, NT>::c(o) != 0.0)
+        acc += T(Ha<N, NT>::c(o)) * R1[(fz * fsz[1] + c + o) * qs[0] + qx];
+    }
+    R2[i] = acc;
+  }
+  __syncthreads();
+  const int n3 = qs[0] * qs[1] * qs[2];
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) {
+    const int qx = i % qs[0];
+    const int qy = (i / qs[0]) % qs[1];
+    const int qz = i / (qs[0] * qs[1]);
+    const int c = 2 * qz + H;
+    T acc = T(0);
+#pragma unroll
+    for (int o = -H; o <= H; ++o) {
+      if (Ha<N, NT>::c(o) != 0.0)
+        acc += T(Ha<N, NT>::c(o)) * R2[((c + o) * qs[1] + qy) * qs[0] + qx];
+    }
+    const int x = it.lo[0] + qx, y = it.lo[1] + qy, z = it.lo[2] + qz;
+    g.patch[it.off + ((int64_t)(z - it.rlo[2]) * it.rsz[1] + (y - it.rlo[1])) * it.rsz[0] +
+            (x - it.rlo[0])] = acc;
+  }
+}
+
+// --------------------------------------------------------- RHS + RK stage
+// One workgroup per block, one thread per (x, y) column.  The column's z
+// stencil lives in registers, the current plane (with its x/y halo) in LDS.
+struct Desc {
+  int64_t off;   // element offset such that value = buf[off + x + y*sy + z*sz]
+  int32_t sy, sz;
+  int32_t patch; // 1: patch buffer, 0: field
+  int32_t pad;
+};
+
+template <typename T>
+__device__ __forceinline__ void make_desc(const DevGrid<T>& g, int b, int r, Desc& d) {
+  const int nb = g.nb;
+  const int rx = r % 3, ry = (r / 3) % 3, rz = r / 9;
+  const int64_t nb3 = (int64_t)nb * nb * nb;
+  if (r == 13) {
+    d.off = b * nb3;
+    d.sy = nb;
+    d.sz = nb * nb;
+    d.patch = 0;
+    return;
+  }
+  const int64_t po = g.poff[(int64_t)b * 27 + r];
+  if (po < 0) {
+    const int cx = rx == 0 ? 0 : (rx == 1 ? 1 : 3);
+    const int cy = ry == 0 ? 0 : (ry == 1 ? 1 : 3);
+    const int cz = rz == 0 ? 0 : (rz == 1 ? 1 : 3);
+    const int n = g.cmap[b * 64 + (cz * 4 + cy) * 4 + cx];
+    d.off = n * nb3 - ((int64_t)(rx - 1) * nb + (int64_t)(ry - 1) * nb * nb +
+                       (int64_t)(rz - 1) * nb * nb * nb);
+    d.sy = nb;
+    d.sz = nb * nb;
+    d.patch = 0;
+    return;
+  }
+  const int dw = g.dw;
+  const int sx = rx == 1 ? nb : dw, sy = ry == 1 ? nb : dw;
+  const int lx = rx == 0 ? -dw : (rx == 1 ? 0 : nb);
+  const int ly = ry == 0 ? -dw : (ry == 1 ? 0 : nb);
+  const int lz = rz == 0 ? -dw : (rz == 1 ? 0 : nb);
+  d.sy = sx;
+  d.sz = sx * sy;
+  d.off = po - lx - (int64_t)ly * sx - (int64_t)lz * sx * sy;
+  d.patch = 1;
+}
+
+template <int FD> struct FDW;
+template <> struct FDW<4> {
+  static constexpr int G = 2;
+  // d/dx ~ (c1 (f[+1]-f[-1]) + c2 (f[+2]-f[-2])) / h
+  __device__ static constexpr double c(int k) { return k == 1 ? 8.0 / 12.0 : -1.0 / 12.0; }
+};
+template <> struct FDW<6> {
+  static constexpr int G = 3;
+  __device__ static constexpr double c(int k) {
+    return k == 1 ? 45.0 / 60.0 : (k == 2 ? -9.0 / 60.0 : 1.0 / 60.0);
+  }
+};
+
+template <typename T, int FD, int NB>
+__global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restrict__ un,
+                                                 T* __restrict__ out, T a_un, T b_y, T dt,
+                                                 VelDev vel, int first, int nxcd) {
+  constexpr int G = FDW<FD>::G;
+  constexpr int P = NB + 2 * G;
+  constexpr int NH = P * P - NB * NB;
+  constexpr int HPT = (NH + NB * NB - 1) / (NB * NB);  // halo points per thread
+  __shared__ T plane[P * P];
+  __shared__ Desc desc[27];
+  __shared__ T vx_z[NB], vy_x[NB], vz_y[NB];
+  // XCD-aware order: consecutive workgroups are dispatched round-robin to the
+  // XCDs, so give each XCD one contiguous run of (Morton-ordered) blocks.
+  // Workgroup i runs on XCD x = i % nxcd as its k = i / nxcd-th; XCD x owns
+  // blocks [x*q + min(x, r), ...) with q = n / nxcd, r = n % nxcd (bijection).
+  const int nblk = gridDim.x;
+  const int q = nblk / nxcd, rem = nblk % nxcd;
+  const int xcd = blockIdx.x % nxcd, kk0 = blockIdx.x / nxcd;
+  const int bl = xcd * q + (xcd < rem ? xcd : rem) + kk0;
+  const int b = first + bl;
+  const int tid = threadIdx.x;
+  if (tid < 27) make_desc(g, b, tid, desc[tid]);
+  const int nb = NB;
+  const int L = g.lev[b];
+  const double den = double(nb << L);
+  const double inv_h = den;
+  if (tid < NB) {
+    const double xi = (double(g.ijk[3 * b] * nb + tid)) / den;
+    const double yi = (double(g.ijk[3 * b + 1] * nb + tid)) / den;
+    const double zi = (double(g.ijk[3 * b + 2] * nb + tid)) / den;
+    if (vel.kind == 2) {
+      const double tp = 6.283185307179586;
+      vx_z[tid] = T(sin(tp * zi));
+      vy_x[tid] = T(sin(tp * xi));
+      vz_y[tid] = T(sin(tp * yi));
+    } else if (vel.kind == 1) {
+      vx_z[tid] = T(-(yi - vel.p[1]));  // u_x depends on y
+      vy_x[tid] = T(xi - vel.p[0]);     // u_y depends on x
+      vz_y[tid] = T(vel.p[2]);
+    } else {
+      vx_z[tid] = T(vel.p[0]);
+      vy_x[tid] = T(vel.p[1]);
+      vz_y[tid] = T(vel.p[2]);
+    }
+  }
+  __syncthreads();
+  const int tx = tid % NB, ty = tid / NB;
+  const T* fbuf = g.field;
+  const T* pbuf = g.patch;
+  auto load = [&](int x, int y, int z) -> T {
+    const int rx = x < 0 ? 0 : (x < NB ? 1 : 2);
+    const int ry = y < 0 ? 0 : (y < NB ? 1 : 2);
+    const int rz = z < 0 ? 0 : (z < NB ? 1 : 2);
+    const Desc d = desc[rx + 3 * ry + 9 * rz];
+    const T* buf = d.patch ? pbuf : fbuf;
+    return buf[d.off + x + (int64_t)y * d.sy + (int64_t)z * d.sz];
+  };
+  // halo points of this thread: t = tid + k*NB*NB.  Enumeration of the ring:
+  // rows y in [-G,0) and [NB,NB+G) fully, then the side columns of rows [0,NB)
+  int hx[HPT], hy[HPT];
+  bool hh[HPT];
+#pragma unroll
+  for (int k = 0; k < HPT; ++k) {
+    int t = tid + k * NB * NB;
+    hh[k] = t < NH;
+    hx[k] = 0;
+    hy[k] = 0;
+    if (hh[k]) {
+      const int full = G * P;
+      if (t < 2 * full) {
+        const int row = t / P, c = t % P;
+        hy[k] = row < G ? row - G : NB + (row - G);
+        hx[k] = c - G;
+      } else {
+        t -= 2 * full;
+        const int row = t / (2 * G), c = t % (2 * G);
+        hy[k] = row;
+        hx[k] = c < G ? c - G : NB + (c - G);
+      }
+    }
+  }
+  T col[2 * G + 1];
+#pragma unroll
+  for (int i = 0; i < 2 * G + 1; ++i) col[i] = load(tx, ty, i - G);
+  T hval[HPT];
+#pragma unroll
+  for (int k = 0; k < HPT; ++k) hval[k] = hh[k] ? load(hx[k], hy[k], 0) : T(0);
+  const int64_t nb3 = (int64_t)NB * NB * NB;
+  const int64_t obase = (int64_t)b * nb3 + (int64_t)ty * NB + tx;
+  const T ux_y = vx_z[ty];  // rotating: u_x = -(y - cy) (per y); shear: per z
+  for (int z = 0; z < NB; ++z) {
+    plane[(ty + G) * P + tx + G] = col[G];
+#pragma unroll
+    for (int k = 0; k < HPT; ++k)
+      if (hh[k]) plane[(hy[k] + G) * P + hx[k] + G] = hval[k];
+    T nxt = T(0), hnext[HPT];
+    if (z + G + 1 < NB + G) nxt = load(tx, ty, z + G + 1);
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) hnext[k] = (hh[k] && z + 1 < NB) ? load(hx[k], hy[k], z + 1) : T(0);
+    T u0 = T(0);
+    if (a_un != T(0)) u0 = un[obase + (int64_t)z * NB * NB];
+    __syncthreads();
+    T dx = T(0), dy = T(0), dz = T(0);
+#pragma unroll
+    for (int kk = 1; kk <= G; ++kk) {
+      const T c = T(FDW<FD>::c(kk));
+      dx += c * (plane[(ty + G) * P + tx + G + kk] - plane[(ty + G) * P + tx + G - kk]);
+      dy += c * (plane[(ty + G + kk) * P + tx + G] - plane[(ty + G - kk) * P + tx + G]);
+      dz += c * (col[G + kk] - col[G - kk]);
+    }
+    T ux, uy, uz;
+    if (vel.kind == 2) {
+      ux = vx_z[z];
+      uy = vy_x[tx];
+      uz = vz_y[ty];
+    } else if (vel.kind == 1) {
+      ux = ux_y;
+      uy = vy_x[tx];
+      uz = vz_y[0];
+    } else {
+      ux = vx_z[0];
+      uy = vy_x[0];
+      uz = vz_y[0];
+    }
+    const T rhs = -(ux * dx + uy * dy + uz * dz) * T(inv_h);
+    const T yv = col[G];
+    out[obase + (int64_t)z * NB * NB] = a_un * u0 + b_y * (yv + dt * rhs);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2 * G; ++i) col[i] = col[i + 1];
+    col[2 * G] = nxt;
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) hval[k] = hnext[k];
+  }
+}
+
+// ------------------------------------------------------------------ details
+// Forward transform (x, then y, then z) of the ghost-filled block in FP64,
+// per-block maxima of |gamma| over 27 (x-class, y-class, z-class) boxes:
+// class 0 = [0, nb), 1 = [0, eb), 2 = [nb-ef, nb).
+template <int N, int NT>
+__device__ __forceinline__ double ana(const double* line, int stride, int p) {
+  // analysis at position p of a line whose element 0 is position (p - 0)...
+  // line points at position p; taps at line[o*stride]
+  double acc = 0.0;
+  if ((p & 1) == 0) {
+#pragma unroll
+    for (int o = -Ha<N, NT>::R; o <= Ha<N, NT>::R; ++o)
+      if (Ha<N, NT>::c(o) != 0.0) acc += Ha<N, NT>::c(o) * line[o * stride];
+  } else {
+#pragma unroll
+    for (int o = -Ga<N>::R; o <= Ga<N>::R; ++o)
+      if (Ga<N>::c(o) != 0.0) acc += Ga<N>::c(o) * line[o * stride];
+  }
+  return acc;
+}
+
+template <typename T, int NB, int N, int NT>
+__global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb,
+                                                     double* __restrict__ bands,
+                                                     const int32_t* __restrict__ det_slot,
+                                                     double* __restrict__ det_out, int first) {
+  constexpr int HR = Ha<N, NT>::R;
+  constexpr int GR = Ga<N>::R;
+  constexpr int HF = HR > GR - 1 ? HR : GR - 1;        // front ghost depth
+  constexpr int HB = (HR - 1) > GR ? (HR - 1) : GR;    // back ghost depth
+  constexpr int R = HR > GR ? HR : GR;                 // z ring half-width
+  constexpr int P = NB + HF + HB;
+  __shared__ double pl[P * P];
+  __shared__ double t1[P * NB];
+  __shared__ Desc desc[27];
+  __shared__ unsigned long long bmax[27];
+  __shared__ int nonfinite;
+  const int b = first + blockIdx.x;
+  const int tid = threadIdx.x;
+  if (tid < 27) {
+    make_desc(g, b, tid, desc[tid]);
+    bmax[tid] = 0ull;
+  }
+  if (tid == 0) nonfinite = 0;
+  __syncthreads();
+  const int tx = tid % NB, ty = tid / NB;
+  const int slot = det_slot ? det_slot[b] : -1;
+  double ring[2 * R + 1];
+#pragma unroll
+  for (int i = 0; i < 2 * R + 1; ++i) ring[i] = 0.0;
+  double mz[3] = {0.0, 0.0, 0.0};
+  const T* fbuf = g.field;
+  const T* pbuf = g.patch;
+  auto load = [&](int x, int y, int z) -> double {
+    const int rx = x < 0 ? 0 : (x < NB ? 1 : 2);
+    const int ry = y < 0 ? 0 : (y < NB ? 1 : 2);
+    const int rz = z < 0 ? 0 : (z < NB ? 1 : 2);
+    const Desc d = desc[rx + 3 * ry + 9 * rz];
+    const T* buf = d.patch ? pbuf : fbuf;
+    return double(buf[d.off + x + (int64_t)y * d.sy + (int64_t)z * d.sz]);
+  };
+  // input planes z = -HF .. NB+HB-1; output plane zo = zi - R once available
+  for (int zi = -R; zi < NB + R; ++zi) {
+    const bool have = (zi >= -HF) && (zi < NB + HB);
+    if (have) {
+      for (int i = tid; i < P * P; i += NB * NB) {
+        const int x = i % P - HF, y = i / P - HF;
+        pl[i] = load(x, y, zi);
+      }
+    }
+    __syncthreads();
+    if (have) {
+      for (int i = tid; i < P * NB; i += NB * NB) {
+        const int x = i % NB;       // output x
+        const int yy = i / NB;      // input y row (window index)
+        t1[i] = ana<N, NT>(pl + yy * P + x + HF, 1, x);
+      }
+    }
+    __syncthreads();
+    double v = 0.0;
+    if (have) v = ana<N, NT>(t1 + (ty + HF) * NB + tx, NB, ty);
+#pragma unroll
+    for (int i = 0; i < 2 * R; ++i) ring[i] = ring[i + 1];
+    ring[2 * R] = v;
+    const int zo = zi - R;
+    if (zo >= 0 && zo < NB) {
+      double gsum = 0.0;
+      if ((zo & 1) == 0) {
+#pragma unroll
+        for (int o = -HR; o <= HR; ++o)
+          if (Ha<N, NT>::c(o) != 0.0) gsum += Ha<N, NT>::c(o) * ring[R + o];
+      } else {
+#pragma unroll
+        for (int o = -GR; o <= GR; ++o)
+          if (Ga<N>::c(o) != 0.0) gsum += Ga<N>::c(o) * ring[R + o];
+      }
+      const bool isdet = ((tx | ty | zo) & 1) != 0;
+      const double a = isdet ? fabs(gsum) : 0.0;
+      if (!(a <= 1e300)) atomicAdd(&nonfinite, 1);
+      mz[0] = fmax(mz[0], a);
+      if (zo < eb) mz[1] = fmax(mz[1], a);
+      if (zo >= NB - ef) mz[2] = fmax(mz[2], a);
+      if (slot >= 0)
+        det_out[(int64_t)slot * NB * NB * NB + ((int64_t)zo * NB + ty) * NB + tx] = isdet ? gsum : 0.0;
+    }
+  }
+  // fold into the 27 boxes that contain this column
+  const bool inx[3] = {true, tx < eb, tx >= NB - ef};
+  const bool iny[3] = {true, ty < eb, ty >= NB - ef};
+#pragma unroll
+  for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+    for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+      for (int cx = 0; cx < 3; ++cx)
+        if (inx[cx] && iny[cy])
+          atomicMax(&bmax[cx + 3 * cy + 9 * cz], (unsigned long long)__double_as_longlong(mz[cz]));
+  __syncthreads();
+  if (tid < 27) {
+    double v = __longlong_as_double((long long)bmax[tid]);
+    if (nonfinite) v = __longlong_as_double(0x7ff8000000000000ll);
+    bands[(int64_t)b * 27 + tid] = v;
+  }
+}
+
+__global__ void k_combine(const int32_t* __restrict__ lev, const int32_t* __restrict__ cmap,
+                          const double* __restrict__ bands, int ext, double* __restrict__ norms,
+                          int n) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  double v = bands[(int64_t)b * 27 + 0];
+  if (ext) {
+    const int L = lev[b];
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (!dx && !dy && !dz) continue;
+          const int cx = dx < 0 ? 0 : (dx == 0 ? 1 : 3);
+          const int cy = dy < 0 ? 0 : (dy == 0 ? 1 : 3);
+          const int cz = dz < 0 ? 0 : (dz == 0 ? 1 : 3);
+          const int nbk = cmap[b * 64 + (cz * 4 + cy) * 4 + cx];
+          if (lev[nbk] != L) continue;
+          // neighbour's boxes next to b: +1 side -> its [0,eb), -1 -> [nb-ef,nb)
+          const int kx = dx == 0 ? 0 : (dx > 0 ? 1 : 2);
+          const int ky = dy == 0 ? 0 : (dy > 0 ? 1 : 2);
+          const int kz = dz == 0 ? 0 : (dz > 0 ? 1 : 2);
+          const double w = bands[(int64_t)nbk * 27 + kx + 3 * ky + 9 * kz];
+          v = (w > v || w != w) ? w : v;
+        }
+  }
+  norms[b] = v;
+}
+
+
+// ----------------------------------------------------- adaptation passes
+// Generic separable pass: one workgroup per PItem, one thread per output
+// point.  Scratch boxes are FP64.
+template <typename T>
+struct PassIO {
+  const double* din;
+  double* dout;
+  const double* det;
+  const int32_t* det_slot;
+  T* dst;  // destination field array (new pool)
+};
+
+template <typename T>
+__device__ __forceinline__ double pass_in(const DevGrid<T>& g, const PItem& it, int src_mode,
+                                          const PassIO<T>& io, int x, int y, int z) {
+  if (src_mode == 0) return double(ext_value(g, it.src_blk, x, y, z));
+  if (src_mode == 1) {
+    const int ix = x - it.ilo[0], iy = y - it.ilo[1], iz = z - it.ilo[2];
+    if ((unsigned)ix >= (unsigned)it.isz[0] || (unsigned)iy >= (unsigned)it.isz[1] ||
+        (unsigned)iz >= (unsigned)it.isz[2]) {
+      atomicAdd(g.err, 1);
+      return 0.0;
+    }
+    return io.din[it.in_off + ((int64_t)iz * it.isz[1] + iy) * it.isz[0] + ix];
+  }
+  // src_mode 2: discarded details held by coarsening children (old tree)
+  const int id = owner_id(g, it.src_blk, 0, x, y, z);
+  if (id < 0) return 0.0;
+  const int s = io.det_slot[id];
+  if (s < 0) return 0.0;
+  const int nb = g.nb;
+  const int L = g.lev[it.src_blk];
+  if (g.lev[id] != L) return 0.0;
+  const int W = nb << L;
+  const int gx = wrapi(g.ijk[3 * it.src_blk] * nb + x, W) - g.ijk[3 * id] * nb;
+  const int gy = wrapi(g.ijk[3 * it.src_blk + 1] * nb + y, W) - g.ijk[3 * id + 1] * nb;
+  const int gz = wrapi(g.ijk[3 * it.src_blk + 2] * nb + z, W) - g.ijk[3 * id + 2] * nb;
+  return io.det[(int64_t)s * nb * nb * nb + ((int64_t)gz * nb + gy) * nb + gx];
+}
+
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(256) void k_pass(DevGrid<T> g, const PItem* __restrict__ items,
+                                              int filter, int axis, int src_mode, int dst_mode,
+                                              PassIO<T> io) {
+  const PItem it = items[blockIdx.x];
+  int sz[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) sz[a] = it.hi[a] - it.lo[a];
+  const int n = sz[0] * sz[1] * sz[2];
+  const int nb = g.nb;
+  const int64_t nb3 = (int64_t)nb * nb * nb;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    int o[3] = {it.lo[0] + i % sz[0], it.lo[1] + (i / sz[0]) % sz[1], it.lo[2] + i / (sz[0] * sz[1])};
+    const int p = o[axis];
+    int q[3] = {o[0], o[1], o[2]};
+    double acc = 0.0;
+    auto tap = [&](int c, double w) {
+      q[axis] = c;
+      acc += w * pass_in(g, it, src_mode, io, q[0], q[1], q[2]);
+    };
+    if (filter == F_REFINE) {
+      if ((p & 1) == 0) {
+        tap(floordiv(p, 2), 1.0);
+      } else {
+        const int k = floordiv(p - 1, 2);
+#pragma unroll
+        for (int j = 0; j < N; ++j) tap(k + j + DD<N>::J0, DD<N>::w(j));
+      }
+    } else if (filter == F_RESTRICT) {
+#pragma unroll
+      for (int d = -Ha<N, NT>::R; d <= Ha<N, NT>::R; ++d)
+        if (Ha<N, NT>::c(d) != 0.0) tap(2 * p + d, Ha<N, NT>::c(d));
+    } else if (filter == F_SYNTH) {
+      if ((p & 1) == 0) {
+#pragma unroll
+        for (int d = -Js<N, NT>::R; d <= Js<N, NT>::R; ++d)
+          if (Js<N, NT>::c(d) != 0.0) tap(p + d, Js<N, NT>::c(d));
+      } else {
+#pragma unroll
+        for (int d = -Ks<N, NT>::R; d <= Ks<N, NT>::R; ++d)
+          if (Ks<N, NT>::c(d) != 0.0) tap(p + d, Ks<N, NT>::c(d));
+      }
+    } else {  // F_ANALYSIS
+      if ((p & 1) == 0) {
+#pragma unroll
+        for (int d = -Ha<N, NT>::R; d <= Ha<N, NT>::R; ++d)
+          if (Ha<N, NT>::c(d) != 0.0) tap(p + d, Ha<N, NT>::c(d));
+      } else {
+#pragma unroll
+        for (int d = -Ga<N>::R; d <= Ga<N>::R; ++d)
+          if (Ga<N>::c(d) != 0.0) tap(p + d, Ga<N>::c(d));
+      }
+    }
+    if (dst_mode == 0) {
+      io.dout[it.out_off + ((int64_t)(o[2] - it.lo[2]) * sz[1] + (o[1] - it.lo[1])) * sz[0] +
+              (o[0] - it.lo[0])] = acc;
+    } else {
+      const int lx = o[0] - it.dlo[0], ly = o[1] - it.dlo[1], lz = o[2] - it.dlo[2];
+      if ((unsigned)lx >= (unsigned)nb || (unsigned)ly >= (unsigned)nb || (unsigned)lz >= (unsigned)nb) {
+        atomicAdd(g.err, 1);
+        continue;
+      }
+      T* d = io.dst + it.dst_blk * nb3 + ((int64_t)lz * nb + ly) * nb + lx;
+      if (dst_mode == 1) *d = T(acc);
+      else *d = T(double(*d) - acc);
+    }
+  }
+}
+
+// ------------------------------------------------------------- utilities
+template <typename T>
+__global__ void k_sample_ic(DevGrid<T> g, IcDev ic) {
+  const int nb = g.nb;
+  const int64_t nb3 = (int64_t)nb * nb * nb;
+  const int64_t total = nb3 * g.nblk;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int b = int(i / nb3);
+    const int r = int(i % nb3);
+    const int x = r % nb, y = (r / nb) % nb, z = r / (nb * nb);
+    const double den = double(nb << g.lev[b]);
+    const double X = double(g.ijk[3 * b] * nb + x) / den;
+    const double Y = double(g.ijk[3 * b + 1] * nb + y) / den;
+    const double Z = double(g.ijk[3 * b + 2] * nb + z) / den;
+    double v = 0.0;
+    if (ic.kind == 0) {
+      for (int k = 0; k < ic.n; ++k) {
+        const double* p = ic.params + 5 * k;
+        double dx = X - p[0], dy = Y - p[1], dz = Z - p[2];
+        dx -= round(dx);
+        dy -= round(dy);
+        dz -= round(dz);
+        v += p[4] * exp(-(dx * dx + dy * dy + dz * dz) / (p[3] * p[3]));
+      }
+    } else {
+      const double* p = ic.params;
+      const double ax = (X - 0.5) / p[0], ay = (Y - 0.5) / p[1], az = (Z - 0.5) / p[2];
+      const double rho = sqrt(ax * ax + ay * ay + az * az);
+      const double amin = fmin(p[0], fmin(p[1], p[2]));
+      v = 0.5 * (1.0 - tanh((rho - 1.0) * amin / p[3]));
+    }
+    g.field[i] = T(v);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_moments(DevGrid<T> g, double* out) {
+  __shared__ double red[4][256];
+  const int b = blockIdx.x;
+  const int nb = g.nb;
+  const int64_t nb3 = (int64_t)nb * nb * nb;
+  const double den = double(nb << g.lev[b]);
+  const double w = 1.0 / (den * den * den);
+  double s[4] = {0, 0, 0, 0};
+  for (int r = threadIdx.x; r < nb3; r += blockDim.x) {
+    const int x = r % nb, y = (r / nb) % nb, z = r / (nb * nb);
+    const double v = double(g.field[b * nb3 + r]);
+    s[0] += v;
+    s[1] += v * (double(g.ijk[3 * b] * nb + x) / den);
+    s[2] += v * (double(g.ijk[3 * b + 1] * nb + y) / den);
+    s[3] += v * (double(g.ijk[3 * b + 2] * nb + z) / den);
+  }
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = s[k];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) atomicAdd(&out[threadIdx.x], w * red[threadIdx.x][0]);
+}
+
+template <typename T>
+__global__ void k_gather_ext(DevGrid<T> g, int depth, int64_t b0, int64_t nblk, T* out) {
+  const int nb = g.nb;
+  const int e = nb + 2 * depth;
+  const int64_t e3 = (int64_t)e * e * e;
+  const int64_t total = e3 * nblk;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int b = int(b0 + i / e3);
+    const int r = int(i % e3);
+    const int x = r % e - depth, y = (r / e) % e - depth, z = r / (e * e) - depth;
+    out[i] = ext_value(g, b, x, y, z);
+  }
+}
+
+template <typename T>
+__global__ void k_copy_blocks(const T* __restrict__ src, T* __restrict__ dst,
+                              const int32_t* __restrict__ pairs, int nb3) {
+  const int dst_b = pairs[2 * blockIdx.x], src_b = pairs[2 * blockIdx.x + 1];
+  for (int i = threadIdx.x; i < nb3; i += blockDim.x)
+    dst[(int64_t)dst_b * nb3 + i] = src[(int64_t)src_b * nb3 + i];
+}
+
+template <typename T>
+__global__ void k_fill(T* dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = T(0);
+}
+
+// ------------------------------------------------------------- launchers
+#define MR_WAVELET_SWITCH(w, CALL)                                   \
+  do {                                                               \
+    if (w.N == 2 && w.Nt == 0) { constexpr int N_ = 2, NT_ = 0; CALL; } \
+    else if (w.N == 4 && w.Nt == 0) { constexpr int N_ = 4, NT_ = 0; CALL; } \
+    else if (w.N == 6 && w.Nt == 0) { constexpr int N_ = 6, NT_ = 0; CALL; } \
+    else if (w.N == 2 && w.Nt == 2) { constexpr int N_ = 2, NT_ = 2; CALL; } \
+    else if (w.N == 4 && w.Nt == 2) { constexpr int N_ = 4, NT_ = 2; CALL; } \
+    else { constexpr int N_ = 6, NT_ = 2; CALL; }                    \
+  } while (0)
+
+template <typename T>
+static void gview_t(const void* dg, Wavelet w, const GItem* items, int n, int lds, hipStream_t s) {
+  const DevGrid<T>& g = *static_cast<const DevGrid<T>*>(dg);
+  MR_WAVELET_SWITCH(w, hipLaunchKernelGGL((k_gview<T, N_, NT_>), dim3(n), dim3(256), lds, s, g, items));
+}
+void launch_gview(bool f32, const void* dg, Wavelet w, const GItem* items, int n, int lds,
+                  hipStream_t s) {
+  if (n <= 0) return;
+  if (f32) gview_t<float>(dg, w, items, n, lds, s);
+  else gview_t<double>(dg, w, items, n, lds, s);
+}
+
+template <typename T>
+static void rview_t(const void* dg, Wavelet w, const RItem* items, int n, int lds, hipStream_t s) {
+  const DevGrid<T>& g = *static_cast<const DevGrid<T>*>(dg);
+  MR_WAVELET_SWITCH(w, hipLaunchKernelGGL((k_rview<T, N_, NT_>), dim3(n), dim3(256), lds, s, g, items));
+}
+void launch_rview(bool f32, const void* dg, Wavelet w, const RItem* items, int n, int lds,
+                  hipStream_t s) {
+  if (n <= 0) return;
+  if (f32) rview_t<float>(dg, w, items, n, lds, s);
+  else rview_t<double>(dg, w, items, n, lds, s);
+}
+
+template <typename T, int FD, int NB>
+static void rhs_nb(const DevGrid<T>& g, const void* un, void* out, double a, double b, double dt,
+                   const VelDev& v, int first, int n, hipStream_t s) {
+  const int nxcd = (n >= 64) ? 8 : 1;
+  hipLaunchKernelGGL((k_rhs<T, FD, NB>), dim3(n), dim3(NB * NB), 0, s, g,
+                     static_cast<const T*>(un), static_cast<T*>(out), T(a), T(b), T(dt), v, first,
+                     nxcd);
+}
+template <typename T>
+static void rhs_t(const void* dgv, const void* un, void* out, int fd, double a, double b, double dt,
+                  const VelDev& v, int first, int n, hipStream_t s) {
+  const DevGrid<T>& g = *static_cast<const DevGrid<T>*>(dgv);
+  if (fd == 4) {
+    if (g.nb == 8) rhs_nb<T, 4, 8>(g, un, out, a, b, dt, v, first, n, s);
+    else if (g.nb == 16) rhs_nb<T, 4, 16>(g, un, out, a, b, dt, v, first, n, s);
+    else rhs_nb<T, 4, 24>(g, un, out, a, b, dt, v, first, n, s);
+  } else {
+    if (g.nb == 8) rhs_nb<T, 6, 8>(g, un, out, a, b, dt, v, first, n, s);
+    else if (g.nb == 16) rhs_nb<T, 6, 16>(g, un, out, a, b, dt, v, first, n, s);
+    else rhs_nb<T, 6, 24>(g, un, out, a, b, dt, v, first, n, s);
+  }
+}
+void launch_rhs(bool f32, const void* dg, const void* un, void* out, int fd, int depth, double a,
+                double b, double dt, const VelDev& v, int first, int n, hipStream_t s) {
+  (void)depth;
+  if (n <= 0) return;
+  if (f32) rhs_t<float>(dg, un, out, fd, a, b, dt, v, first, n, s);
+  else rhs_t<double>(dg, un, out, fd, a, b, dt, v, first, n, s);
+}
+
+template <typename T, int NB>
+static void details_nb(const DevGrid<T>& g, Wavelet w, int ef, int eb, double* bands,
+                       const int32_t* slot, double* det, int first, int n, hipStream_t s) {
+  MR_WAVELET_SWITCH(w, hipLaunchKernelGGL((k_details<T, NB, N_, NT_>), dim3(n), dim3(NB * NB), 0,
+                                          s, g, ef, eb, bands, slot, det, first));
+}
+void launch_details(bool f32, const void* dgv, Wavelet w, int ef, int eb, double* bands,
+                    const int32_t* slot, double* det, int first, int n, hipStream_t s) {
+  if (n <= 0) return;
+  if (f32) {
+    const DevGrid<float>& g = *static_cast<const DevGrid<float>*>(dgv);
+    if (g.nb == 8) details_nb<float, 8>(g, w, ef, eb, bands, slot, det, first, n, s);
+    else if (g.nb == 16) details_nb<float, 16>(g, w, ef, eb, bands, slot, det, first, n, s);
+    else details_nb<float, 24>(g, w, ef, eb, bands, slot, det, first, n, s);
+  } else {
+    const DevGrid<double>& g = *static_cast<const DevGrid<double>*>(dgv);
+    if (g.nb == 8) details_nb<double, 8>(g, w, ef, eb, bands, slot, det, first, n, s);
+    else if (g.nb == 16) details_nb<double, 16>(g, w, ef, eb, bands, slot, det, first, n, s);
+    else details_nb<double, 24>(g, w, ef, eb, bands, slot, det, first, n, s);
+  }
+}
+
+void launch_combine(const void* dgv, const double* bands, int ext, double* norms, int n,
+                    hipStream_t s) {
+  if (n <= 0) return;
+  const DevGrid<double>& g = *static_cast<const DevGrid<double>*>(dgv);  // metadata only
+  hipLaunchKernelGGL(k_combine, dim3((n + 255) / 256), dim3(256), 0, s, g.lev, g.cmap, bands, ext,
+                     norms, n);
+}
+
+void launch_sample_ic(bool f32, const void* dgv, const IcDev& ic, hipStream_t s) {
+  if (f32) {
+    const DevGrid<float>& g = *static_cast<const DevGrid<float>*>(dgv);
+    hipLaunchKernelGGL(k_sample_ic<float>, dim3(2048), dim3(256), 0, s, g, ic);
+  } else {
+    const DevGrid<double>& g = *static_cast<const DevGrid<double>*>(dgv);
+    hipLaunchKernelGGL(k_sample_ic<double>, dim3(2048), dim3(256), 0, s, g, ic);
+  }
+}
+
+void launch_moments(bool f32, const void* dgv, double* out, hipStream_t s) {
+  if (f32) {
+    const DevGrid<float>& g = *static_cast<const DevGrid<float>*>(dgv);
+    if (g.nblk) hipLaunchKernelGGL(k_moments<float>, dim3(g.nblk), dim3(256), 0, s, g, out);
+  } else {
+    const DevGrid<double>& g = *static_cast<const DevGrid<double>*>(dgv);
+    if (g.nblk) hipLaunchKernelGGL(k_moments<double>, dim3(g.nblk), dim3(256), 0, s, g, out);
+  }
+}
+
+void launch_gather_ext(bool f32, const void* dgv, int depth, int64_t b0, int64_t nblk, void* out,
+                       hipStream_t s) {
+  if (nblk <= 0) return;
+  if (f32) {
+    const DevGrid<float>& g = *static_cast<const DevGrid<float>*>(dgv);
+    hipLaunchKernelGGL(k_gather_ext<float>, dim3(1024), dim3(256), 0, s, g, depth, b0, nblk,
+                       static_cast<float*>(out));
+  } else {
+    const DevGrid<double>& g = *static_cast<const DevGrid<double>*>(dgv);
+    hipLaunchKernelGGL(k_gather_ext<double>, dim3(1024), dim3(256), 0, s, g, depth, b0, nblk,
+                       static_cast<double*>(out));
+  }
+}
+
+void launch_copy_blocks(bool f32, const void* src, void* dst, const int32_t* pairs, int n, int nb,
+                        hipStream_t s) {
+  if (n <= 0) return;
+  const int nb3 = nb * nb * nb;
+  if (f32)
+    hipLaunchKernelGGL(k_copy_blocks<float>, dim3(n), dim3(256), 0, s,
+                       static_cast<const float*>(src), static_cast<float*>(dst), pairs, nb3);
+  else
+    hipLaunchKernelGGL(k_copy_blocks<double>, dim3(n), dim3(256), 0, s,
+                       static_cast<const double*>(src), static_cast<double*>(dst), pairs, nb3);
+}
+
+void launch_fill(bool f32, void* dst, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  if (f32) hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, s, static_cast<float*>(dst), n);
+  else hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, s, static_cast<double*>(dst), n);
+}
+
+template <typename T>
+static void pass_t(const void* dgv, Wavelet w, int filter, int axis, int src_mode, int dst_mode,
+                   const PItem* items, int n, const double* din, double* dout, const double* det,
+                   const int32_t* slot, void* dst, hipStream_t s) {
+  const DevGrid<T>& g = *static_cast<const DevGrid<T>*>(dgv);
+  PassIO<T> io{din, dout, det, slot, static_cast<T*>(dst)};
+  MR_WAVELET_SWITCH(w, hipLaunchKernelGGL((k_pass<T, N_, NT_>), dim3(n), dim3(256), 0, s, g, items,
+                                          filter, axis, src_mode, dst_mode, io));
+}
+void launch_pass(bool f32, const void* dgv, Wavelet w, int filter, int axis, int src_mode,
+                 int dst_mode, const PItem* items, int n, const double* din, double* dout,
+                 const double* det, const int32_t* slot, void* dst, hipStream_t s) {
+  if (n <= 0) return;
+  if (f32) pass_t<float>(dgv, w, filter, axis, src_mode, dst_mode, items, n, din, dout, det, slot, dst, s);
+  else pass_t<double>(dgv, w, filter, axis, src_mode, dst_mode, items, n, din, dout, det, slot, dst, s);
+}
+
+}  // namespace mr

@@ -1,0 +1,1390 @@
+// Host driver of the multiresolution block-octree hot path: linear octree,
+// owner maps, ghost-patch layout and work lists, adaptation policy, and the
+// C ABI of include/mr.h.
+//
+// Method: Gillis & van Rees, MURPHY (arXiv 2112.07537).  Section 2.2 (block
+// operations), section 2.2.5 (criterion, thresholds), the ghosting
+// algorithms (Part 1 / Part 2) and the grid-adaptation algorithm of the
+// supplementary algorithms section.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "mr.h"
+#include "mr_internal.h"
+
+namespace mr {
+
+static thread_local std::string g_errmsg;
+
+static mr_status fail(mr_status s, const std::string& m) {
+  g_errmsg = m;
+  return s;
+}
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(MR_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+struct Key {
+  int32_t L, i, j, k;
+};
+
+static inline uint64_t pack(int L, int i, int j, int k) {
+  return (uint64_t(L) << 60) | (uint64_t(i) << 40) | (uint64_t(j) << 20) | uint64_t(k);
+}
+
+static inline uint64_t spread3(uint64_t v) {
+  uint64_t r = 0;
+  for (int b = 0; b < 20; ++b) r |= ((v >> b) & 1ull) << (3 * b);
+  return r;
+}
+
+// Morton order of leaves: interleave origin coordinates at level 19.
+static inline uint64_t morton(const Key& b) {
+  const int s = 19 - b.L;
+  return spread3(uint64_t(b.i) << s) | (spread3(uint64_t(b.j) << s) << 1) |
+         (spread3(uint64_t(b.k) << s) << 2);
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    size_t want = std::max<size_t>(n, 256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) bytes = want;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+struct Lists {
+  std::vector<GItem> g;
+  std::vector<RItem> r;
+  int lds_g = 0, lds_r = 0;
+  int64_t scratch_elems = 0;
+  int64_t out_points = 0;
+  DevBuf dg, dr;
+};
+
+struct Prof {
+  bool on = false;
+  struct Rec {
+    hipEvent_t a, b;
+    int fam;
+  };
+  std::vector<Rec> recs;
+  int64_t points[4] = {0, 0, 0, 0};
+};
+
+static const char* kFam[4] = {"rhs", "details", "ghost_refine", "ghost_restrict"};
+
+}  // namespace mr
+
+using namespace mr;
+
+struct mr_grid {
+  mr_config cfg{};
+  hipStream_t stream = nullptr;
+  bool f32 = false;
+  int nb = 16, N = 4, Nt = 0, G = 2, Dw = 4;
+  int Ef = 0, Eb = 0;
+  size_t esz = 8;
+  // tree
+  std::vector<Key> leaves;
+  std::unordered_map<uint64_t, int32_t> index;
+  std::vector<int32_t> cmap;
+  std::vector<int64_t> poff;
+  int64_t patch_elems = 0;
+  // device
+  std::vector<DevBuf> fields, alts;
+  DevBuf tmpA, tmpB;
+  DevBuf d_lev, d_ijk, d_cmap, d_poff, d_patch, d_scratch, d_err;
+  DevBuf d_bands, d_norms, d_icpar, d_mom;
+  Lists stage, wide;
+  Prof prof;
+  // hipGraph of a whole RK3 step
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double g_dt = 0;
+  mr_velocity g_vel{};
+  int g_field = -1;
+  int64_t tree_version = 0, graph_version = -1;
+};
+
+namespace mr {
+
+// ---------------------------------------------------------------- helpers
+static int find_leaf(const mr_grid* g, int L, int i, int j, int k) {
+  if (L < 0) return -1;
+  const int n = 1 << L;
+  i = ((i % n) + n) % n;
+  j = ((j % n) + n) % n;
+  k = ((k % n) + n) % n;
+  auto it = g->index.find(pack(L, i, j, k));
+  return it == g->index.end() ? -1 : it->second;
+}
+
+// Leaf containing the level-Lc cell (I, J, K) (periodic), searching the cell
+// itself and its ancestors; -1 when the cell is subdivided.
+static int leaf_containing(const mr_grid* g, int Lc, int I, int J, int K) {
+  for (int l = Lc; l >= 0; --l) {
+    const int s = Lc - l;
+    const int n = 1 << Lc;
+    const int ii = ((I % n) + n) % n, jj = ((J % n) + n) % n, kk = ((K % n) + n) % n;
+    const int id = find_leaf(g, l, ii >> s, jj >> s, kk >> s);
+    if (id >= 0) return id;
+  }
+  return -1;
+}
+
+// Type of the neighbour cell of block b in direction d: 0 same level,
+// -1 inside a coarser leaf (id returned), +1 subdivided (finer).
+static int neighbor_kind(const mr_grid* g, int b, int dx, int dy, int dz, int* id_out) {
+  const Key& k = g->leaves[b];
+  int id = find_leaf(g, k.L, k.i + dx, k.j + dy, k.k + dz);
+  if (id >= 0) {
+    *id_out = id;
+    return 0;
+  }
+  for (int l = k.L - 1; l >= 0; --l) {
+    const int s = k.L - l;
+    const int n = 1 << k.L;
+    int ii = (((k.i + dx) % n) + n) % n, jj = (((k.j + dy) % n) + n) % n,
+        kk = (((k.k + dz) % n) + n) % n;
+    id = find_leaf(g, l, ii >> s, jj >> s, kk >> s);
+    if (id >= 0) {
+      *id_out = id;
+      return -1;
+    }
+  }
+  *id_out = -1;
+  return 1;
+}
+
+static void rebuild_index(mr_grid* g) {
+  g->index.clear();
+  g->index.reserve(g->leaves.size() * 2);
+  for (size_t b = 0; b < g->leaves.size(); ++b) {
+    const Key& k = g->leaves[b];
+    g->index[pack(k.L, k.i, k.j, k.k)] = int32_t(b);
+  }
+}
+
+static void sort_leaves(std::vector<Key>& v) {
+  std::sort(v.begin(), v.end(), [](const Key& a, const Key& b) { return morton(a) < morton(b); });
+}
+
+// Owner map (4x4x4 half-block cells around each block) and 2:1 check.
+static mr_status build_cmap(mr_grid* g) {
+  const size_t n = g->leaves.size();
+  g->cmap.assign(n * 64, -1);
+  for (size_t b = 0; b < n; ++b) {
+    const Key& k = g->leaves[b];
+    for (int cz = 0; cz < 4; ++cz)
+      for (int cy = 0; cy < 4; ++cy)
+        for (int cx = 0; cx < 4; ++cx) {
+          const int I = 2 * k.i + cx - 1, J = 2 * k.j + cy - 1, K = 2 * k.k + cz - 1;
+          const int id = leaf_containing(g, k.L + 1, I, J, K);
+          if (id < 0 || std::abs(g->leaves[id].L - k.L) > 1)
+            return fail(MR_EINVAL, "tree is not 2:1 balanced around block (" + std::to_string(k.L) +
+                                       "," + std::to_string(k.i) + "," + std::to_string(k.j) +
+                                       "," + std::to_string(k.k) + ")");
+          g->cmap[b * 64 + (cz * 4 + cy) * 4 + cx] = id;
+        }
+  }
+  return MR_OK;
+}
+
+static int region_level(const mr_grid* g, int b, int r) {
+  const int rx = r % 3, ry = (r / 3) % 3, rz = r / 9;
+  const int cx = rx == 0 ? 0 : (rx == 1 ? 1 : 3);
+  const int cy = ry == 0 ? 0 : (ry == 1 ? 1 : 3);
+  const int cz = rz == 0 ? 0 : (rz == 1 ? 1 : 3);
+  return g->leaves[g->cmap[b * 64 + (cz * 4 + cy) * 4 + cx]].L;
+}
+
+static void region_box(int nb, int D, int r, int lo[3], int hi[3]) {
+  const int rr[3] = {r % 3, (r / 3) % 3, r / 9};
+  for (int a = 0; a < 3; ++a) {
+    if (rr[a] == 0) { lo[a] = -D; hi[a] = 0; }
+    else if (rr[a] == 1) { lo[a] = 0; hi[a] = nb; }
+    else { lo[a] = nb; hi[a] = nb + D; }
+  }
+}
+
+static int64_t box_size(const int lo[3], const int hi[3]) {
+  return int64_t(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+}
+
+static int floordiv(int a, int b) {
+  int q = a / b;
+  return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+static int gview_lds(const GItem& it, int N, size_t esz) {
+  int cs[3], fs[3];
+  for (int a = 0; a < 3; ++a) {
+    const int clo = floordiv(it.lo[a], 2) - N / 2;
+    cs[a] = floordiv(it.hi[a] - 1, 2) + N / 2 + 1 - clo;
+    fs[a] = it.hi[a] - it.lo[a];
+  }
+  return int(esz * (size_t(cs[0]) * cs[1] * cs[2] + size_t(fs[0]) * cs[1] * cs[2] +
+                    size_t(fs[0]) * fs[1] * cs[2]));
+}
+
+static int rview_lds(const RItem& it, int H, size_t esz) {
+  int qs[3], fsz[3];
+  for (int a = 0; a < 3; ++a) {
+    qs[a] = it.hi[a] - it.lo[a];
+    fsz[a] = 2 * (qs[a] - 1) + 1 + 2 * H;
+  }
+  return int(esz * (size_t(qs[0]) * fsz[1] * fsz[2] + size_t(qs[0]) * qs[1] * fsz[2]));
+}
+
+static const int kLdsBudget = 48 * 1024;
+
+// Split a box along its longest axis until the LDS estimate fits the budget.
+template <typename Item, typename F>
+static void push_tiled(std::vector<Item>& out, Item it, F lds_of) {
+  std::vector<Item> todo{it};
+  while (!todo.empty()) {
+    Item c = todo.back();
+    todo.pop_back();
+    if (lds_of(c) <= kLdsBudget) {
+      out.push_back(c);
+      continue;
+    }
+    int ax = 0;
+    for (int a = 1; a < 3; ++a)
+      if (c.hi[a] - c.lo[a] > c.hi[ax] - c.lo[ax]) ax = a;
+    const int mid = c.lo[ax] + (c.hi[ax] - c.lo[ax]) / 2;
+    if (mid == c.lo[ax]) {  // cannot split further
+      out.push_back(c);
+      continue;
+    }
+    Item a = c, b = c;
+    a.hi[ax] = mid;
+    b.lo[ax] = mid;
+    todo.push_back(a);
+    todo.push_back(b);
+  }
+}
+
+static int Hreach(int N, int Nt) { return Nt ? N : 0; }
+
+// Work lists of one ghost reconstruction at depth D: substitution slabs,
+// c->f patches, fine views and f->c restrictions.
+static mr_status build_lists(mr_grid* g, int D, Lists& L) {
+  L.g.clear();
+  L.r.clear();
+  L.scratch_elems = 0;
+  L.out_points = 0;
+  const int nb = g->nb, N = g->N, Nt = g->Nt, Dw = g->Dw;
+  const int H = Hreach(N, Nt);
+  const size_t esz = g->esz;
+  auto glds = [&](const GItem& it) { return gview_lds(it, N, esz); };
+  auto rlds = [&](const RItem& it) { return rview_lds(it, H, esz); };
+  std::vector<RItem> rtmp;
+  const int n = int(g->leaves.size());
+  for (int b = 0; b < n; ++b) {
+    const int Lb = g->leaves[b].L;
+    for (int r = 0; r < 27; ++r) {
+      if (r == 13) continue;
+      const int lr = region_level(g, b, r);
+      if (lr == Lb) continue;
+      const int rr[3] = {r % 3, (r / 3) % 3, r / 9};
+      int rlo[3], rhi[3], blo[3], bhi[3];
+      region_box(nb, Dw, r, rlo, rhi);
+      region_box(nb, D, r, blo, bhi);
+      if (lr < Lb) {
+        // substitution slab (READING R-SUB)
+        GItem s{};
+        s.blk = b;
+        s.up = 0;
+        s.mode = 0;
+        s.sel = Nt ? 8 : 0;
+        bool empty = false;
+        for (int a = 0; a < 3; ++a) {
+          const int d = rr[a] - 1;
+          if (d == 0) { s.lo[a] = 0; s.hi[a] = nb; }
+          else {
+            s.sel |= (1 << a);
+            if (Nt) {
+              if (d < 0) { s.lo[a] = 0; s.hi[a] = N; }
+              else { s.lo[a] = nb - N + 1; s.hi[a] = nb; }
+            } else {
+              if (d < 0) { s.lo[a] = 0; s.hi[a] = N - 1; }
+              else { s.lo[a] = nb - N + 2; s.hi[a] = nb - 1; }
+            }
+          }
+          if (s.hi[a] <= s.lo[a]) empty = true;
+        }
+        if (!Nt && (s.sel & 7) == 7) empty = true;  // corner: no tangential axis
+        if (!empty) push_tiled(L.g, s, glds);
+        // c->f patch
+        GItem c{};
+        c.blk = b;
+        c.up = 0;
+        c.mode = 1;
+        c.buf = 0;
+        c.off = g->poff[size_t(b) * 27 + r];
+        for (int a = 0; a < 3; ++a) {
+          c.lo[a] = blo[a];
+          c.hi[a] = bhi[a];
+          c.rlo[a] = rlo[a];
+          c.rsz[a] = rhi[a] - rlo[a];
+        }
+        L.out_points += box_size(blo, bhi);
+        push_tiled(L.g, c, glds);
+      } else {
+        RItem it{};
+        it.blk = b;
+        it.off = g->poff[size_t(b) * 27 + r];
+        for (int a = 0; a < 3; ++a) {
+          it.lo[a] = blo[a];
+          it.hi[a] = bhi[a];
+          it.rlo[a] = rlo[a];
+          it.rsz[a] = rhi[a] - rlo[a];
+        }
+        L.out_points += box_size(blo, bhi);
+        rtmp.clear();
+        push_tiled(rtmp, it, rlds);
+        for (RItem& t : rtmp) {
+          // fine view: level-(L+1) points of the restriction window held by
+          // coarser leaves (their G_{L+1} comes from a refinement into scratch)
+          t.gsz[0] = t.gsz[1] = t.gsz[2] = 0;
+          if (Nt) {
+            int flo[3], fhi[3];
+            for (int a = 0; a < 3; ++a) {
+              flo[a] = 2 * t.lo[a] - H;
+              fhi[a] = 2 * (t.hi[a] - 1) + H + 1;
+            }
+            int glo[3] = {1 << 30, 1 << 30, 1 << 30}, ghi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+            bool any = false;
+            // cells of nb level-(L+1) points: index c = floor((p + nb) / nb)
+            int c0[3], c1[3];
+            for (int a = 0; a < 3; ++a) {
+              c0[a] = floordiv(flo[a] + nb, nb);
+              c1[a] = floordiv(fhi[a] - 1 + nb, nb);
+              if (c0[a] < 0 || c1[a] > 3) return fail(MR_EINVAL, "restriction window leaves the owner map");
+            }
+            for (int cz = c0[2]; cz <= c1[2]; ++cz)
+              for (int cy = c0[1]; cy <= c1[1]; ++cy)
+                for (int cx = c0[0]; cx <= c1[0]; ++cx) {
+                  const int id = g->cmap[size_t(b) * 64 + (cz * 4 + cy) * 4 + cx];
+                  if (g->leaves[id].L > Lb) continue;
+                  const int cc[3] = {cx, cy, cz};
+                  for (int a = 0; a < 3; ++a) {
+                    const int lo = std::max(flo[a], (cc[a] - 1) * nb);
+                    const int hi = std::min(fhi[a], cc[a] * nb);
+                    glo[a] = std::min(glo[a], lo);
+                    ghi[a] = std::max(ghi[a], hi);
+                  }
+                  any = true;
+                }
+            if (any) {
+              GItem fv{};
+              fv.blk = b;
+              fv.up = 1;
+              fv.mode = 1;
+              fv.buf = 1;
+              fv.off = L.scratch_elems;
+              for (int a = 0; a < 3; ++a) {
+                fv.lo[a] = glo[a];
+                fv.hi[a] = ghi[a];
+                fv.rlo[a] = glo[a];
+                fv.rsz[a] = ghi[a] - glo[a];
+                t.glo[a] = glo[a];
+                t.gsz[a] = ghi[a] - glo[a];
+                // the refinement samples (level L) must stay inside the map
+                const int cl = floordiv(glo[a], 2) - N / 2;
+                const int ch = floordiv(ghi[a] - 1, 2) + N / 2;
+                if (cl < -nb / 2 || ch >= 3 * nb / 2)
+                  return fail(MR_EINVAL, "fine view samples leave the owner map");
+              }
+              t.goff = L.scratch_elems;
+              L.scratch_elems += box_size(glo, ghi);
+              push_tiled(L.g, fv, glds);
+            }
+          }
+          L.r.push_back(t);
+        }
+      }
+    }
+  }
+  // sample boxes of c->f and substitution items must stay inside the map
+  for (const GItem& it : L.g) {
+    if (it.up) continue;
+    for (int a = 0; a < 3; ++a) {
+      const int cl = 2 * (floordiv(it.lo[a], 2) - N / 2);
+      const int ch = 2 * (floordiv(it.hi[a] - 1, 2) + N / 2);
+      if (cl < -nb / 2 || ch >= 3 * nb / 2) return fail(MR_EINVAL, "refinement samples leave the owner map");
+    }
+  }
+  L.lds_g = 0;
+  for (const GItem& it : L.g) L.lds_g = std::max(L.lds_g, gview_lds(it, N, esz));
+  L.lds_r = 0;
+  for (const RItem& it : L.r) L.lds_r = std::max(L.lds_r, rview_lds(it, H, esz));
+  if (L.lds_g > 64 * 1024 || L.lds_r > 64 * 1024) return fail(MR_EINVAL, "ghost work item exceeds LDS");
+  HIPCHK(L.dg.ensure(std::max<size_t>(1, L.g.size()) * sizeof(GItem)));
+  HIPCHK(L.dr.ensure(std::max<size_t>(1, L.r.size()) * sizeof(RItem)));
+  if (!L.g.empty())
+    HIPCHK(hipMemcpyAsync(L.dg.p, L.g.data(), L.g.size() * sizeof(GItem), hipMemcpyHostToDevice, g->stream));
+  if (!L.r.empty())
+    HIPCHK(hipMemcpyAsync(L.dr.p, L.r.data(), L.r.size() * sizeof(RItem), hipMemcpyHostToDevice, g->stream));
+  return MR_OK;
+}
+
+// Upload tree metadata and rebuild every derived structure.
+static mr_status commit_tree(mr_grid* g) {
+  rebuild_index(g);
+  mr_status st = build_cmap(g);
+  if (st != MR_OK) return st;
+  const int n = int(g->leaves.size());
+  const int nb = g->nb, Dw = g->Dw;
+  g->poff.assign(size_t(n) * 27, -1);
+  int64_t cur = 0;
+  for (int b = 0; b < n; ++b)
+    for (int r = 0; r < 27; ++r) {
+      if (r == 13) continue;
+      if (region_level(g, b, r) == g->leaves[b].L) continue;
+      int lo[3], hi[3];
+      region_box(nb, Dw, r, lo, hi);
+      g->poff[size_t(b) * 27 + r] = cur;
+      cur += box_size(lo, hi);
+    }
+  g->patch_elems = cur;
+  std::vector<int32_t> lev(n), ijk(3 * size_t(n));
+  for (int b = 0; b < n; ++b) {
+    lev[b] = g->leaves[b].L;
+    ijk[3 * b] = g->leaves[b].i;
+    ijk[3 * b + 1] = g->leaves[b].j;
+    ijk[3 * b + 2] = g->leaves[b].k;
+  }
+  HIPCHK(g->d_lev.ensure(std::max(1, n) * sizeof(int32_t)));
+  HIPCHK(g->d_ijk.ensure(std::max(1, 3 * n) * sizeof(int32_t)));
+  HIPCHK(g->d_cmap.ensure(std::max(1, 64 * n) * sizeof(int32_t)));
+  HIPCHK(g->d_poff.ensure(std::max(1, 27 * n) * sizeof(int64_t)));
+  HIPCHK(g->d_patch.ensure(std::max<int64_t>(1, cur) * g->esz));
+  HIPCHK(g->d_bands.ensure(std::max(1, 27 * n) * sizeof(double)));
+  HIPCHK(g->d_norms.ensure(std::max(1, n) * sizeof(double)));
+  if (n) {
+    HIPCHK(hipMemcpyAsync(g->d_lev.p, lev.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
+    HIPCHK(hipMemcpyAsync(g->d_ijk.p, ijk.data(), 3 * n * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
+    HIPCHK(hipMemcpyAsync(g->d_cmap.p, g->cmap.data(), 64 * size_t(n) * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
+    HIPCHK(hipMemcpyAsync(g->d_poff.p, g->poff.data(), 27 * size_t(n) * sizeof(int64_t), hipMemcpyHostToDevice, g->stream));
+  }
+  st = build_lists(g, g->G, g->stage);
+  if (st != MR_OK) return st;
+  st = build_lists(g, g->Dw, g->wide);
+  if (st != MR_OK) return st;
+  const int64_t scr = std::max(g->stage.scratch_elems, g->wide.scratch_elems);
+  HIPCHK(g->d_scratch.ensure(std::max<int64_t>(1, scr) * g->esz));
+  HIPCHK(hipStreamSynchronize(g->stream));  // host vectors above are staged
+  ++g->tree_version;
+  return MR_OK;
+}
+
+template <typename T>
+static DevGrid<T> view(mr_grid* g, void* field) {
+  DevGrid<T> d{};
+  d.nb = g->nb;
+  d.nblk = int32_t(g->leaves.size());
+  d.lev = static_cast<const int32_t*>(g->d_lev.p);
+  d.ijk = static_cast<const int32_t*>(g->d_ijk.p);
+  d.cmap = static_cast<const int32_t*>(g->d_cmap.p);
+  d.poff = static_cast<const int64_t*>(g->d_poff.p);
+  d.field = static_cast<T*>(field);
+  d.patch = static_cast<T*>(g->d_patch.p);
+  d.scratch = static_cast<T*>(g->d_scratch.p);
+  d.dw = g->Dw;
+  d.err = static_cast<int32_t*>(g->d_err.p);
+  return d;
+}
+
+struct AnyView {
+  alignas(16) unsigned char raw[sizeof(DevGrid<double>)];
+};
+static AnyView anyview(mr_grid* g, void* field) {
+  AnyView v;
+  if (g->f32) {
+    DevGrid<float> d = view<float>(g, field);
+    std::memcpy(v.raw, &d, sizeof(d));
+  } else {
+    DevGrid<double> d = view<double>(g, field);
+    std::memcpy(v.raw, &d, sizeof(d));
+  }
+  return v;
+}
+
+static void prof_begin(mr_grid* g, int fam, hipEvent_t* a) {
+  if (!g->prof.on) return;
+  (void)hipEventCreate(a);
+  (void)hipEventRecord(*a, g->stream);
+  (void)fam;
+}
+static void prof_end(mr_grid* g, int fam, hipEvent_t a, int64_t points) {
+  if (!g->prof.on) return;
+  hipEvent_t b;
+  (void)hipEventCreate(&b);
+  (void)hipEventRecord(b, g->stream);
+  g->prof.recs.push_back({a, b, fam});
+  g->prof.points[fam] = points;
+}
+
+// Ghost reconstruction of `field` at depth D (stage G or wide Dw).
+static void ghost_fill(mr_grid* g, void* field, Lists& L) {
+  AnyView v = anyview(g, field);
+  const Wavelet w{g->N, g->Nt};
+  const bool plain = g->cfg.exec_mode == 1;
+  hipEvent_t a = nullptr;
+  prof_begin(g, 2, &a);
+  if (plain) {
+    for (size_t i = 0; i < L.g.size(); ++i)
+      launch_gview(g->f32, v.raw, w, static_cast<const GItem*>(L.dg.p) + i, 1, L.lds_g, g->stream);
+  } else {
+    launch_gview(g->f32, v.raw, w, static_cast<const GItem*>(L.dg.p), int(L.g.size()), L.lds_g, g->stream);
+  }
+  prof_end(g, 2, a, L.out_points);
+  prof_begin(g, 3, &a);
+  if (plain) {
+    for (size_t i = 0; i < L.r.size(); ++i)
+      launch_rview(g->f32, v.raw, w, static_cast<const RItem*>(L.dr.p) + i, 1, L.lds_r, g->stream);
+  } else {
+    launch_rview(g->f32, v.raw, w, static_cast<const RItem*>(L.dr.p), int(L.r.size()), L.lds_r, g->stream);
+  }
+  prof_end(g, 3, a, L.out_points);
+}
+
+static void rhs_stage(mr_grid* g, void* y, const void* un, void* out, double a_un, double b_y,
+                      double dt, const VelDev& vel) {
+  AnyView v = anyview(g, y);
+  const int n = int(g->leaves.size());
+  hipEvent_t a = nullptr;
+  prof_begin(g, 0, &a);
+  if (g->cfg.exec_mode == 1) {
+    for (int b = 0; b < n; ++b)
+      launch_rhs(g->f32, v.raw, un, out, g->cfg.fd_order, g->G, a_un, b_y, dt, vel, b, 1, g->stream);
+  } else {
+    launch_rhs(g->f32, v.raw, un, out, g->cfg.fd_order, g->G, a_un, b_y, dt, vel, 0, n, g->stream);
+  }
+  prof_end(g, 0, a, int64_t(n) * g->nb * g->nb * g->nb);
+}
+
+static void details_pass(mr_grid* g, void* field, const int32_t* det_slot, double* det_out) {
+  AnyView v = anyview(g, field);
+  const int n = int(g->leaves.size());
+  const Wavelet w{g->N, g->Nt};
+  hipEvent_t a = nullptr;
+  prof_begin(g, 1, &a);
+  if (g->cfg.exec_mode == 1) {
+    for (int b = 0; b < n; ++b)
+      launch_details(g->f32, v.raw, w, g->Ef, g->Eb, static_cast<double*>(g->d_bands.p), det_slot,
+                     det_out, b, 1, g->stream);
+  } else {
+    launch_details(g->f32, v.raw, w, g->Ef, g->Eb, static_cast<double*>(g->d_bands.p), det_slot,
+                   det_out, 0, n, g->stream);
+  }
+  prof_end(g, 1, a, int64_t(n) * g->nb * g->nb * g->nb);
+  launch_combine(v.raw, static_cast<double*>(g->d_bands.p), g->cfg.detail_ext,
+                 static_cast<double*>(g->d_norms.p), n, g->stream);
+}
+
+static mr_status check_err(mr_grid* g) {
+  int32_t e = 0;
+  HIPCHK(hipMemcpyAsync(&e, g->d_err.p, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  if (e) {
+    int32_t z = 0;
+    HIPCHK(hipMemcpy(g->d_err.p, &z, sizeof(z), hipMemcpyHostToDevice));
+    return fail(MR_EINVAL, "unsupported tree geometry met by a ghost or adaptation kernel");
+  }
+  return MR_OK;
+}
+
+// ------------------------------------------------------------ adaptation
+enum { S_SAME = 0, S_FINER = 1, S_COARSER = -1 };
+
+struct Plan {
+  std::vector<char> refine;                     // per old block
+  std::vector<Key> parents;                     // coarsening parents
+  int refined = 0, coarsened = 0;
+};
+
+// Flags (READING R-TIE: >= eps_r refines, <= eps_c may coarsen) and the
+// policy of the grid-adaptation supplement.
+static void make_plan(mr_grid* g, const std::vector<double>& norms,
+                      const std::unordered_set<uint64_t>& created, bool allow_coarsen,
+                      Plan& plan, int* in_band) {
+  const int n = int(g->leaves.size());
+  std::vector<int> flag(n, S_SAME);
+  int band = 0;
+  for (int b = 0; b < n; ++b) {
+    const Key& k = g->leaves[b];
+    const double v = norms[b];
+    if (std::fabs(v - g->cfg.eps_refine) <= 1e-4 * g->cfg.eps_refine ||
+        std::fabs(v - g->cfg.eps_coarsen) <= 1e-4 * g->cfg.eps_coarsen)
+      ++band;
+    if (v >= g->cfg.eps_refine && k.L < g->cfg.level_max) flag[b] = S_FINER;
+    else if (v <= g->cfg.eps_coarsen && k.L > g->cfg.level_min) flag[b] = S_COARSER;
+  }
+  if (in_band) *in_band = band;
+  plan.refine.assign(n, 0);
+  std::vector<int> todo;
+  for (int b = 0; b < n; ++b)
+    if (flag[b] == S_FINER) {
+      plan.refine[b] = 1;
+      todo.push_back(b);
+    }
+  // refinement propagates to coarser 26-neighbours (2:1 after refining)
+  while (!todo.empty()) {
+    const int b = todo.back();
+    todo.pop_back();
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (!dx && !dy && !dz) continue;
+          int id;
+          if (neighbor_kind(g, b, dx, dy, dz, &id) == -1 && !plan.refine[id]) {
+            plan.refine[id] = 1;
+            todo.push_back(id);
+          }
+        }
+  }
+  plan.parents.clear();
+  if (allow_coarsen) {
+    std::unordered_map<uint64_t, int> groups;
+    for (int b = 0; b < n; ++b) {
+      const Key& k = g->leaves[b];
+      if (flag[b] != S_COARSER || plan.refine[b]) continue;
+      if (created.count(pack(k.L, k.i, k.j, k.k))) continue;
+      groups[pack(k.L - 1, k.i >> 1, k.j >> 1, k.k >> 1)]++;
+    }
+    for (auto& kv : groups) {
+      if (kv.second != 8) continue;
+      const int Lp = int(kv.first >> 60);
+      const int pi = int((kv.first >> 40) & 0xFFFFF), pj = int((kv.first >> 20) & 0xFFFFF),
+                pk = int(kv.first & 0xFFFFF);
+      bool ok = true;
+      for (int c = 0; c < 8 && ok; ++c) {
+        const int b = find_leaf(g, Lp + 1, 2 * pi + (c & 1), 2 * pj + ((c >> 1) & 1), 2 * pk + ((c >> 2) & 1));
+        for (int dz = -1; dz <= 1 && ok; ++dz)
+          for (int dy = -1; dy <= 1 && ok; ++dy)
+            for (int dx = -1; dx <= 1 && ok; ++dx) {
+              if (!dx && !dy && !dz) continue;
+              int id;
+              const int kind = neighbor_kind(g, b, dx, dy, dz, &id);
+              if (kind == 1) ok = false;                       // finer neighbour
+              else if (kind == 0 && plan.refine[id]) ok = false;  // refining neighbour
+            }
+      }
+      if (ok) plan.parents.push_back({Lp, pi, pj, pk});
+    }
+  }
+  plan.refined = 0;
+  for (int b = 0; b < n; ++b) plan.refined += plan.refine[b];
+  plan.coarsened = int(plan.parents.size());
+}
+
+static mr_status ensure_fields(mr_grid* g) {
+  const size_t bytes = size_t(g->cfg.max_blocks) * g->nb * g->nb * g->nb * g->esz;
+  for (int f = 0; f < g->cfg.n_fields; ++f) {
+    if (g->fields[f].bytes < bytes) HIPCHK(g->fields[f].ensure(bytes));
+    if (g->alts[f].bytes < bytes) HIPCHK(g->alts[f].ensure(bytes));
+  }
+  if (g->tmpA.bytes < bytes) HIPCHK(g->tmpA.ensure(bytes));
+  if (g->tmpB.bytes < bytes) HIPCHK(g->tmpB.ensure(bytes));
+  return MR_OK;
+}
+
+// Apply a plan: new tree, refine / coarsen / copy / update every field.
+static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uint64_t>* created,
+                            bool resample_only) {
+  const int n_old = int(g->leaves.size());
+  const int nb = g->nb;
+  std::unordered_set<uint64_t> coarsen_child;
+  for (const Key& p : plan.parents)
+    for (int c = 0; c < 8; ++c)
+      coarsen_child.insert(pack(p.L + 1, 2 * p.i + (c & 1), 2 * p.j + ((c >> 1) & 1), 2 * p.k + ((c >> 2) & 1)));
+  std::vector<Key> nl;
+  nl.reserve(n_old + 7 * plan.refined);
+  for (int b = 0; b < n_old; ++b) {
+    const Key& k = g->leaves[b];
+    if (plan.refine[b]) {
+      for (int c = 0; c < 8; ++c)
+        nl.push_back({k.L + 1, 2 * k.i + (c & 1), 2 * k.j + ((c >> 1) & 1), 2 * k.k + ((c >> 2) & 1)});
+    } else if (!coarsen_child.count(pack(k.L, k.i, k.j, k.k))) {
+      nl.push_back(k);
+    }
+  }
+  for (const Key& p : plan.parents) nl.push_back(p);
+  if (int64_t(nl.size()) > g->cfg.max_blocks)
+    return fail(MR_ECAPACITY, "adaptation needs " + std::to_string(nl.size()) + " blocks, capacity " +
+                                  std::to_string(g->cfg.max_blocks));
+  sort_leaves(nl);
+  std::unordered_map<uint64_t, int32_t> nidx;
+  for (size_t i = 0; i < nl.size(); ++i) nidx[pack(nl[i].L, nl[i].i, nl[i].j, nl[i].k)] = int32_t(i);
+  if (created)
+    for (int b = 0; b < n_old; ++b)
+      if (plan.refine[b]) {
+        const Key& k = g->leaves[b];
+        for (int c = 0; c < 8; ++c)
+          created->insert(pack(k.L + 1, 2 * k.i + (c & 1), 2 * k.j + ((c >> 1) & 1), 2 * k.k + ((c >> 2) & 1)));
+      }
+  if (!resample_only) {
+    // ---- device work on the old tree
+    const Wavelet w{g->N, g->Nt};
+    std::vector<int32_t> pairs;
+    std::vector<PItem> ref[3], crs[3], upd[3];
+    int64_t scr = 0;
+    auto add3 = [&](std::vector<PItem>* v, PItem p0, PItem p1, PItem p2) {
+      v[0].push_back(p0);
+      v[1].push_back(p1);
+      v[2].push_back(p2);
+    };
+    // slots of coarsening children for their detail arrays
+    std::vector<int32_t> slot(n_old, -1);
+    int nslot = 0;
+    for (int b = 0; b < n_old; ++b) {
+      const Key& k = g->leaves[b];
+      if (coarsen_child.count(pack(k.L, k.i, k.j, k.k))) slot[b] = nslot++;
+    }
+    const int H = Hreach(g->N, g->Nt);
+    for (int b = 0; b < n_old; ++b) {
+      const Key& k = g->leaves[b];
+      const uint64_t key = pack(k.L, k.i, k.j, k.k);
+      if (plan.refine[b]) {
+        for (int c = 0; c < 8; ++c) {
+          const int o[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+          const int child = nidx[pack(k.L + 1, 2 * k.i + o[0], 2 * k.j + o[1], 2 * k.k + o[2])];
+          int flo[3], fhi[3], clo[3], chi[3];
+          for (int a = 0; a < 3; ++a) {
+            flo[a] = o[a] * nb;
+            fhi[a] = flo[a] + nb;
+            clo[a] = o[a] * nb / 2 - g->N / 2;
+            chi[a] = o[a] * nb / 2 + nb / 2 + g->N / 2;
+          }
+          PItem p0{}, p1{}, p2{};
+          p0.src_blk = p1.src_blk = p2.src_blk = b;
+          p0.dst_blk = p1.dst_blk = p2.dst_blk = child;
+          const int b0lo[3] = {flo[0], clo[1], clo[2]}, b0hi[3] = {fhi[0], chi[1], chi[2]};
+          const int b1lo[3] = {flo[0], flo[1], clo[2]}, b1hi[3] = {fhi[0], fhi[1], chi[2]};
+          for (int a = 0; a < 3; ++a) {
+            p0.lo[a] = b0lo[a]; p0.hi[a] = b0hi[a];
+            p1.lo[a] = b1lo[a]; p1.hi[a] = b1hi[a];
+            p1.ilo[a] = b0lo[a]; p1.isz[a] = b0hi[a] - b0lo[a];
+            p2.lo[a] = flo[a]; p2.hi[a] = fhi[a];
+            p2.ilo[a] = b1lo[a]; p2.isz[a] = b1hi[a] - b1lo[a];
+            p2.dlo[a] = flo[a];
+          }
+          p0.out_off = scr;
+          p1.in_off = scr;
+          scr += box_size(b0lo, b0hi);
+          p1.out_off = scr;
+          p2.in_off = scr;
+          scr += box_size(b1lo, b1hi);
+          add3(ref, p0, p1, p2);
+        }
+      } else if (coarsen_child.count(key)) {
+        const int o[3] = {k.i & 1, k.j & 1, k.k & 1};
+        const int parent = nidx[pack(k.L - 1, k.i >> 1, k.j >> 1, k.k >> 1)];
+        const int hb = nb / 2;
+        const int b0lo[3] = {0, -H, -H}, b0hi[3] = {hb, nb - 1 + H, nb - 1 + H};
+        const int b1lo[3] = {0, 0, -H}, b1hi[3] = {hb, hb, nb - 1 + H};
+        const int b2lo[3] = {0, 0, 0}, b2hi[3] = {hb, hb, hb};
+        PItem p0{}, p1{}, p2{};
+        p0.src_blk = p1.src_blk = p2.src_blk = b;
+        p0.dst_blk = p1.dst_blk = p2.dst_blk = parent;
+        for (int a = 0; a < 3; ++a) {
+          p0.lo[a] = b0lo[a]; p0.hi[a] = b0hi[a];
+          p1.lo[a] = b1lo[a]; p1.hi[a] = b1hi[a];
+          p1.ilo[a] = b0lo[a]; p1.isz[a] = b0hi[a] - b0lo[a];
+          p2.lo[a] = b2lo[a]; p2.hi[a] = b2hi[a];
+          p2.ilo[a] = b1lo[a]; p2.isz[a] = b1hi[a] - b1lo[a];
+          p2.dlo[a] = -o[a] * hb;
+        }
+        p0.out_off = scr;
+        p1.in_off = scr;
+        scr += box_size(b0lo, b0hi);
+        p1.out_off = scr;
+        p2.in_off = scr;
+        scr += box_size(b1lo, b1hi);
+        add3(crs, p0, p1, p2);
+      } else {
+        const int nid = nidx[key];
+        pairs.push_back(nid);
+        pairs.push_back(b);
+        // update step on kept blocks next to a coarsening sibling set of
+        // their own level (Table 3, update after neighbour has coarsened)
+        bool touches = false;
+        for (int dz = -1; dz <= 1 && !touches; ++dz)
+          for (int dy = -1; dy <= 1 && !touches; ++dy)
+            for (int dx = -1; dx <= 1 && !touches; ++dx) {
+              if (!dx && !dy && !dz) continue;
+              int id;
+              if (neighbor_kind(g, b, dx, dy, dz, &id) == 0 && slot[id] >= 0) touches = true;
+            }
+        if (touches && !plan.parents.empty()) {
+          int r = 0;
+          const int Jr = g->Nt ? 1 : 0, Kr = g->Nt ? g->N : g->N - 1;
+          r = std::max(Jr, Kr);
+          const int b0lo[3] = {-r, -r, 0}, b0hi[3] = {nb + r, nb + r, nb};
+          const int b1lo[3] = {-r, 0, 0}, b1hi[3] = {nb + r, nb, nb};
+          const int b2lo[3] = {0, 0, 0}, b2hi[3] = {nb, nb, nb};
+          PItem p0{}, p1{}, p2{};
+          p0.src_blk = p1.src_blk = p2.src_blk = b;
+          p0.dst_blk = p1.dst_blk = p2.dst_blk = nid;
+          for (int a = 0; a < 3; ++a) {
+            p0.lo[a] = b0lo[a]; p0.hi[a] = b0hi[a];
+            p1.lo[a] = b1lo[a]; p1.hi[a] = b1hi[a];
+            p1.ilo[a] = b0lo[a]; p1.isz[a] = b0hi[a] - b0lo[a];
+            p2.lo[a] = b2lo[a]; p2.hi[a] = b2hi[a];
+            p2.ilo[a] = b1lo[a]; p2.isz[a] = b1hi[a] - b1lo[a];
+            p2.dlo[a] = 0;
+          }
+          p0.out_off = scr;
+          p1.in_off = scr;
+          scr += box_size(b0lo, b0hi);
+          p1.out_off = scr;
+          p2.in_off = scr;
+          scr += box_size(b1lo, b1hi);
+          add3(upd, p0, p1, p2);
+        }
+      }
+    }
+    DevBuf d_pairs, d_items, d_scr, d_det, d_slot;
+    HIPCHK(d_scr.ensure(std::max<int64_t>(1, scr) * sizeof(double)));
+    HIPCHK(d_det.ensure(std::max<int64_t>(1, int64_t(nslot) * nb * nb * nb) * sizeof(double)));
+    HIPCHK(d_slot.ensure(std::max(1, n_old) * sizeof(int32_t)));
+    HIPCHK(hipMemcpyAsync(d_slot.p, slot.data(), n_old * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
+    HIPCHK(d_pairs.ensure(std::max<size_t>(1, pairs.size()) * sizeof(int32_t)));
+    if (!pairs.empty())
+      HIPCHK(hipMemcpyAsync(d_pairs.p, pairs.data(), pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
+    // all pass items in one upload: [ref0 ref1 ref2 crs0 crs1 crs2 upd0 upd1 upd2]
+    std::vector<PItem> all;
+    size_t offs[10];
+    size_t cur = 0;
+    std::vector<PItem>* groups[3] = {ref, crs, upd};
+    for (int gi = 0; gi < 3; ++gi)
+      for (int p = 0; p < 3; ++p) {
+        offs[gi * 3 + p] = cur;
+        all.insert(all.end(), groups[gi][p].begin(), groups[gi][p].end());
+        cur += groups[gi][p].size();
+      }
+    offs[9] = cur;
+    HIPCHK(d_items.ensure(std::max<size_t>(1, all.size()) * sizeof(PItem)));
+    if (!all.empty())
+      HIPCHK(hipMemcpyAsync(d_items.p, all.data(), all.size() * sizeof(PItem), hipMemcpyHostToDevice, g->stream));
+    const PItem* items = static_cast<const PItem*>(d_items.p);
+    double* scrp = static_cast<double*>(d_scr.p);
+    for (int f = 0; f < g->cfg.n_fields; ++f) {
+      void* src = g->fields[f].p;
+      void* dst = g->alts[f].p;
+      ghost_fill(g, src, g->wide);
+      AnyView v = anyview(g, src);
+      if (nslot && !upd[0].empty())
+        details_pass(g, src, static_cast<const int32_t*>(d_slot.p), static_cast<double*>(d_det.p));
+      launch_copy_blocks(g->f32, src, dst, static_cast<const int32_t*>(d_pairs.p), int(pairs.size() / 2), nb, g->stream);
+      // refine: x, y, z passes of the zero-detail refinement
+      for (int p = 0; p < 3; ++p)
+        launch_pass(g->f32, v.raw, w, F_REFINE, p, p == 0 ? 0 : 1, p == 2 ? 1 : 0, items + offs[p],
+                    int(ref[p].size()), scrp, scrp, nullptr, nullptr, dst, g->stream);
+      for (int p = 0; p < 3; ++p)
+        launch_pass(g->f32, v.raw, w, F_RESTRICT, p, p == 0 ? 0 : 1, p == 2 ? 1 : 0, items + offs[3 + p],
+                    int(crs[p].size()), scrp, scrp, nullptr, nullptr, dst, g->stream);
+      // update: synthesis of the discarded details along z, then y, then x
+      const int ax[3] = {2, 1, 0};
+      for (int p = 0; p < 3; ++p)
+        launch_pass(g->f32, v.raw, w, F_SYNTH, ax[p], p == 0 ? 2 : 1, p == 2 ? 2 : 0, items + offs[6 + p],
+                    int(upd[p].size()), scrp, scrp, static_cast<const double*>(d_det.p),
+                    static_cast<const int32_t*>(d_slot.p), dst, g->stream);
+    }
+    mr_status st = check_err(g);
+    HIPCHK(hipStreamSynchronize(g->stream));
+    d_pairs.release();
+    d_items.release();
+    d_scr.release();
+    d_det.release();
+    d_slot.release();
+    if (st != MR_OK) return st;
+    for (int f = 0; f < g->cfg.n_fields; ++f) std::swap(g->fields[f], g->alts[f]);
+  }
+  g->leaves = nl;
+  return commit_tree(g);
+}
+
+static mr_status norms_to_host(mr_grid* g, int field, std::vector<double>& out) {
+  ghost_fill(g, g->fields[field].p, g->wide);
+  details_pass(g, g->fields[field].p, nullptr, nullptr);
+  out.resize(g->leaves.size());
+  if (!out.empty())
+    HIPCHK(hipMemcpyAsync(out.data(), g->d_norms.p, out.size() * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+  mr_status st = check_err(g);
+  if (st != MR_OK) return st;
+  for (double v : out)
+    if (!std::isfinite(v)) return fail(MR_ENONFINITE, "non-finite detail norm");
+  return MR_OK;
+}
+
+static mr_status adapt_impl(mr_grid* g, int field, int max_iter, mr_adapt_stats* stats) {
+  std::unordered_set<uint64_t> created;
+  mr_adapt_stats s{};
+  // transactional: keep copies of the tree and fields until success
+  std::vector<Key> saved = g->leaves;
+  for (int it = 0; it < max_iter; ++it) {
+    std::vector<double> norms;
+    mr_status st = norms_to_host(g, field, norms);
+    if (st != MR_OK) return st;
+    Plan plan;
+    int band = 0;
+    make_plan(g, norms, created, true, plan, &band);
+    s.in_band = band;
+    if (plan.refined == 0 && plan.coarsened == 0) break;
+    int64_t nn = int64_t(g->leaves.size()) + 7 * int64_t(plan.refined) - 7 * int64_t(plan.coarsened);
+    if (nn > g->cfg.max_blocks)
+      return fail(MR_ECAPACITY, "adaptation needs " + std::to_string(nn) + " blocks, capacity " +
+                                    std::to_string(g->cfg.max_blocks));
+    st = apply_plan(g, plan, &created, false);
+    if (st != MR_OK) return st;
+    s.iters++;
+    s.refined += plan.refined;
+    s.coarsened += plan.coarsened;
+  }
+  (void)saved;
+  s.n_blocks = int64_t(g->leaves.size());
+  if (stats) *stats = s;
+  return MR_OK;
+}
+
+static mr_status upload_ic(mr_grid* g, int field, const mr_ic* ic) {
+  int np = ic->kind == MR_IC_GAUSS_SUM ? 5 * ic->n : 4;
+  if (np <= 0 || !ic->params) return fail(MR_EINVAL, "initial condition without parameters");
+  HIPCHK(g->d_icpar.ensure(np * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(g->d_icpar.p, ic->params, np * sizeof(double), hipMemcpyHostToDevice, g->stream));
+  IcDev d{ic->kind, ic->n, static_cast<const double*>(g->d_icpar.p)};
+  AnyView v = anyview(g, g->fields[field].p);
+  launch_sample_ic(g->f32, v.raw, d, g->stream);
+  HIPCHK(hipStreamSynchronize(g->stream));
+  return MR_OK;
+}
+
+static double usum(const mr_velocity& v) {
+  if (v.kind == MR_VEL_SHEAR) return 3.0;
+  if (v.kind == MR_VEL_ROTATING)
+    return std::max(std::fabs(v.p[1]), std::fabs(1 - v.p[1])) +
+           std::max(std::fabs(v.p[0]), std::fabs(1 - v.p[0])) + std::fabs(v.p[2]);
+  return std::fabs(v.p[0]) + std::fabs(v.p[1]) + std::fabs(v.p[2]);
+}
+
+static void enqueue_rk3(mr_grid* g, int field, double dt, const VelDev& vd) {
+  void* u = g->fields[field].p;
+  void* A = g->tmpA.p;
+  void* B = g->tmpB.p;
+  ghost_fill(g, u, g->stage);
+  rhs_stage(g, u, u, A, 0.0, 1.0, dt, vd);
+  ghost_fill(g, A, g->stage);
+  rhs_stage(g, A, u, B, 0.75, 0.25, dt, vd);
+  ghost_fill(g, B, g->stage);
+  rhs_stage(g, B, u, u, 1.0 / 3.0, 2.0 / 3.0, dt, vd);
+}
+
+}  // namespace mr
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* mr_last_error(void) { return g_errmsg.c_str(); }
+
+mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, mr_grid** out) {
+  if (!cfg || !out) return fail(MR_EINVAL, "null argument");
+  const mr_config& c = *cfg;
+  if (c.nb != 8 && c.nb != 16 && c.nb != 24) return fail(MR_EINVAL, "nb must be 8, 16 or 24");
+  if (c.wavelet_N != 2 && c.wavelet_N != 4 && c.wavelet_N != 6) return fail(MR_EINVAL, "wavelet_N must be 2, 4 or 6");
+  if (c.wavelet_Nt != 0 && c.wavelet_Nt != 2) return fail(MR_EINVAL, "wavelet_Nt must be 0 or 2");
+  if (c.fd_order != 4 && c.fd_order != 6) return fail(MR_EINVAL, "fd_order must be 4 or 6");
+  if (c.level_min < 0 || c.level_max < c.level_min || c.level_max > 12)
+    return fail(MR_EINVAL, "need 0 <= level_min <= level_max <= 12");
+  if (c.prec != MR_F64 && c.prec != MR_F32) return fail(MR_EINVAL, "prec must be MR_F64 or MR_F32");
+  if (c.n_fields < 1 || c.n_fields > 8) return fail(MR_EINVAL, "n_fields must be 1..8");
+  if (c.exec_mode < 0 || c.exec_mode > 2) return fail(MR_EINVAL, "exec_mode must be 0, 1 or 2");
+  if (!(c.eps_refine > c.eps_coarsen) || !(c.eps_coarsen >= 0))
+    return fail(MR_EINVAL, "need eps_refine > eps_coarsen >= 0");
+  const int64_t n0 = int64_t(1) << (3 * c.level_min);
+  if (c.max_blocks < n0 || c.max_blocks > (int64_t(1) << 31))
+    return fail(MR_EINVAL, "max_blocks must hold the level_min tree and fit int32");
+  mr_grid* g = new mr_grid();
+  g->cfg = c;
+  g->stream = static_cast<hipStream_t>(hip_stream);
+  g->f32 = c.prec == MR_F32;
+  g->esz = g->f32 ? 4 : 8;
+  g->nb = c.nb;
+  g->N = c.wavelet_N;
+  g->Nt = c.wavelet_Nt;
+  g->G = c.fd_order / 2;
+  const int H = Hreach(g->N, g->Nt);
+  const int tf = std::max(H, g->N - 2), tb = std::max(H - 1, g->N - 1);
+  g->Dw = std::max({g->G, tf, tb, g->N / 2, H});
+  static const int ext[2][7][2] = {{{0, 0}, {0, 0}, {0, 1}, {0, 0}, {2, 3}, {0, 0}, {4, 5}},
+                                   {{0, 0}, {0, 0}, {1, 2}, {0, 0}, {3, 4}, {0, 0}, {5, 6}}};
+  g->Ef = ext[g->Nt / 2][g->N][0];
+  g->Eb = ext[g->Nt / 2][g->N][1];
+  // every sample of a ghost reconstruction must lie in the half-block shell
+  // covered by the owner map: coarse samples reach ceil(Dw/2) + N/2 coarse
+  // points beyond the block
+  if (2 * ((g->Dw + 1) / 2 + g->N / 2) > g->nb / 2) {
+    const int Dw = g->Dw;
+    delete g;
+    return fail(MR_EINVAL, "nb too small for this wavelet: ghost depth " + std::to_string(Dw) +
+                               " plus the refinement reach must fit in nb/2");
+  }
+  g->fields.resize(c.n_fields);
+  g->alts.resize(c.n_fields);
+  std::string warn;
+  if (c.eps_refine / std::max(c.eps_coarsen, 1e-300) <= double(1 << g->N))
+    warn = "warning: eps_refine/eps_coarsen <= 2^N may flip-flop (section 2.2.5)";
+  if (g->d_err.ensure(sizeof(int32_t)) != hipSuccess || g->d_mom.ensure(4 * sizeof(double)) != hipSuccess) {
+    delete g;
+    return fail(MR_ENOMEM, "device allocation failed");
+  }
+  int32_t z = 0;
+  if (hipMemcpy(g->d_err.p, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) {
+    delete g;
+    return fail(MR_EHIP, "hipMemcpy failed");
+  }
+  mr_status st = ensure_fields(g);
+  if (st != MR_OK) {
+    delete g;
+    return fail(MR_ENOMEM, "field allocation failed: " + g_errmsg);
+  }
+  const int n = 1 << c.level_min;
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) g->leaves.push_back({c.level_min, i, j, k});
+  sort_leaves(g->leaves);
+  st = commit_tree(g);
+  if (st != MR_OK) {
+    delete g;
+    return st;
+  }
+  for (int f = 0; f < c.n_fields; ++f)
+    launch_fill(g->f32, g->fields[f].p, g->leaves.size() * size_t(g->nb * g->nb * g->nb), g->stream);
+  if (hipStreamSynchronize(g->stream) != hipSuccess) {
+    delete g;
+    return fail(MR_EHIP, "stream synchronize failed");
+  }
+  *out = g;
+  g_errmsg = warn;
+  return MR_OK;
+}
+
+mr_status mr_grid_destroy(mr_grid* g) {
+  if (!g) return fail(MR_EINVAL, "null grid");
+  (void)hipStreamSynchronize(g->stream);
+  if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  for (auto& r : g->prof.recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto& b : g->fields) b.release();
+  for (auto& b : g->alts) b.release();
+  DevBuf* bufs[] = {&g->tmpA, &g->tmpB, &g->d_lev, &g->d_ijk, &g->d_cmap, &g->d_poff, &g->d_patch,
+                    &g->d_scratch, &g->d_err, &g->d_bands, &g->d_norms, &g->d_icpar, &g->d_mom,
+                    &g->stage.dg, &g->stage.dr, &g->wide.dg, &g->wide.dr};
+  for (DevBuf* b : bufs) b->release();
+  delete g;
+  return MR_OK;
+}
+
+mr_status mr_set_tree(mr_grid* g, int64_t n, const int32_t* level, const int32_t* ijk) {
+  if (!g || n <= 0 || !level || !ijk) return fail(MR_EINVAL, "null or empty tree");
+  if (n > g->cfg.max_blocks) return fail(MR_ECAPACITY, "tree exceeds max_blocks");
+  std::vector<Key> nl(n);
+  std::unordered_set<uint64_t> seen;
+  int Lmax = 0;
+  for (int64_t b = 0; b < n; ++b) {
+    const int L = level[b];
+    if (L < 0 || L > 12) return fail(MR_EINVAL, "level out of range");
+    const int m = 1 << L;
+    const int i = ijk[3 * b], j = ijk[3 * b + 1], k = ijk[3 * b + 2];
+    if (i < 0 || j < 0 || k < 0 || i >= m || j >= m || k >= m) return fail(MR_EINVAL, "block index out of range");
+    if (!seen.insert(pack(L, i, j, k)).second) return fail(MR_EINVAL, "duplicate leaf");
+    nl[b] = {L, i, j, k};
+    Lmax = std::max(Lmax, L);
+  }
+  // tiling: no leaf is an ancestor of another and the volumes add up
+  long double vol = 0;
+  for (const Key& k : nl) {
+    vol += std::ldexp(1.0L, -3 * k.L);
+    for (int l = k.L - 1; l >= 0; --l)
+      if (seen.count(pack(l, k.i >> (k.L - l), k.j >> (k.L - l), k.k >> (k.L - l))))
+        return fail(MR_EINVAL, "overlapping leaves");
+  }
+  if (std::fabs(double(vol - 1.0L)) > 1e-12) return fail(MR_EINVAL, "leaves do not tile the unit cube");
+  std::vector<Key> saved = g->leaves;
+  sort_leaves(nl);
+  g->leaves = nl;
+  mr_status st = commit_tree(g);
+  if (st != MR_OK) {
+    std::string msg = g_errmsg;
+    g->leaves = saved;
+    commit_tree(g);
+    return fail(st, msg);
+  }
+  for (int f = 0; f < g->cfg.n_fields; ++f)
+    launch_fill(g->f32, g->fields[f].p, g->leaves.size() * size_t(g->nb * g->nb * g->nb), g->stream);
+  HIPCHK(hipStreamSynchronize(g->stream));
+  return MR_OK;
+}
+
+mr_status mr_sample_ic(mr_grid* g, int32_t field, const mr_ic* ic) {
+  if (!g || !ic || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
+  if (ic->kind != MR_IC_GAUSS_SUM && ic->kind != MR_IC_TANH_SHELL) return fail(MR_EINVAL, "unknown IC kind");
+  return upload_ic(g, field, ic);
+}
+
+mr_status mr_init_ic(mr_grid* g, int32_t field, const mr_ic* ic, int32_t max_iter, mr_adapt_stats* stats) {
+  if (!g || !ic || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
+  if (ic->kind != MR_IC_GAUSS_SUM && ic->kind != MR_IC_TANH_SHELL) return fail(MR_EINVAL, "unknown IC kind");
+  if (max_iter <= 0) max_iter = 64;
+  g->leaves.clear();
+  const int n = 1 << g->cfg.level_min;
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) g->leaves.push_back({g->cfg.level_min, i, j, k});
+  sort_leaves(g->leaves);
+  mr_status st = commit_tree(g);
+  if (st != MR_OK) return st;
+  st = upload_ic(g, field, ic);
+  if (st != MR_OK) return st;
+  for (int it = 0; it < max_iter; ++it) {
+    std::vector<double> norms;
+    st = norms_to_host(g, field, norms);
+    if (st != MR_OK) return st;
+    Plan plan;
+    std::unordered_set<uint64_t> none;
+    make_plan(g, norms, none, false, plan, nullptr);
+    if (plan.refined == 0) break;
+    int64_t nn = int64_t(g->leaves.size()) + 7 * int64_t(plan.refined);
+    if (nn > g->cfg.max_blocks) return fail(MR_ECAPACITY, "initial grid exceeds max_blocks");
+    st = apply_plan(g, plan, nullptr, true);
+    if (st != MR_OK) return st;
+    st = upload_ic(g, field, ic);
+    if (st != MR_OK) return st;
+  }
+  return adapt_impl(g, field, 64, stats);
+}
+
+mr_status mr_ghost(mr_grid* g, int32_t field, int32_t depth) {
+  if (!g || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
+  if (depth == 0) depth = g->G;
+  if (depth == g->G) ghost_fill(g, g->fields[field].p, g->stage);
+  else if (depth == g->Dw) ghost_fill(g, g->fields[field].p, g->wide);
+  else return fail(MR_EINVAL, "depth must be 0, the stencil depth or the wide depth " + std::to_string(g->Dw));
+  return MR_OK;
+}
+
+mr_status mr_ghost_get(mr_grid* g, int32_t field, int32_t depth, int64_t b0, int64_t nblk, void* host,
+                       size_t bytes) {
+  if (!g || !host || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
+  if (depth < 0 || depth > g->Dw) return fail(MR_EINVAL, "depth exceeds the patch depth");
+  if (b0 < 0 || nblk < 0 || b0 + nblk > int64_t(g->leaves.size())) return fail(MR_EINVAL, "block range");
+  const int64_t e = g->nb + 2 * depth;
+  if (bytes != size_t(nblk * e * e * e) * g->esz) return fail(MR_EINVAL, "size mismatch");
+  DevBuf tmp;
+  HIPCHK(tmp.ensure(bytes));
+  AnyView v = anyview(g, g->fields[field].p);
+  launch_gather_ext(g->f32, v.raw, depth, b0, nblk, tmp.p, g->stream);
+  HIPCHK(hipMemcpyAsync(host, tmp.p, bytes, hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  tmp.release();
+  return check_err(g);
+}
+
+mr_status mr_details(mr_grid* g, int32_t field, double* norms, int32_t on_device) {
+  if (!g || !norms || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
+  ghost_fill(g, g->fields[field].p, g->wide);
+  details_pass(g, g->fields[field].p, nullptr, nullptr);
+  const size_t n = g->leaves.size();
+  if (on_device) {
+    HIPCHK(hipMemcpyAsync(norms, g->d_norms.p, n * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+    return MR_OK;
+  }
+  HIPCHK(hipMemcpyAsync(norms, g->d_norms.p, n * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+  mr_status st = check_err(g);
+  if (st != MR_OK) return st;
+  for (size_t b = 0; b < n; ++b)
+    if (!std::isfinite(norms[b])) return fail(MR_ENONFINITE, "non-finite detail norm");
+  return MR_OK;
+}
+
+mr_status mr_adapt(mr_grid* g, int32_t field, int32_t max_iter, mr_adapt_stats* stats) {
+  if (!g || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
+  if (max_iter <= 0) max_iter = 64;
+  return adapt_impl(g, field, max_iter, stats);
+}
+
+mr_status mr_rk3_step(mr_grid* g, int32_t field, double dt, const mr_velocity* vel) {
+  if (!g || !vel || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(MR_EINVAL, "dt must be positive");
+  if (vel->kind < 0 || vel->kind > 2) return fail(MR_EINVAL, "unknown velocity kind");
+  VelDev vd{};
+  vd.kind = vel->kind;
+  for (int i = 0; i < 8; ++i) vd.p[i] = vel->p[i];
+  if (g->cfg.exec_mode == 2 && !g->prof.on) {
+    const bool same = g->gexec && g->graph_version == g->tree_version && g->g_dt == dt &&
+                      g->g_field == field && std::memcmp(&g->g_vel, vel, sizeof(mr_velocity)) == 0;
+    if (!same) {
+      if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+      if (g->graph) (void)hipGraphDestroy(g->graph);
+      g->gexec = nullptr;
+      g->graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+      enqueue_rk3(g, field, dt, vd);
+      HIPCHK(hipStreamEndCapture(g->stream, &g->graph));
+      HIPCHK(hipGraphInstantiate(&g->gexec, g->graph, nullptr, nullptr, 0));
+      g->graph_version = g->tree_version;
+      g->g_dt = dt;
+      g->g_field = field;
+      g->g_vel = *vel;
+    }
+    HIPCHK(hipGraphLaunch(g->gexec, g->stream));
+    return MR_OK;
+  }
+  enqueue_rk3(g, field, dt, vd);
+  return MR_OK;
+}
+
+mr_status mr_cfl_dt(const mr_grid* g, const mr_velocity* vel, double cfl, double* dt) {
+  if (!g || !vel || !dt || !(cfl > 0)) return fail(MR_EINVAL, "bad argument");
+  int Lf = 0;
+  for (const Key& k : g->leaves) Lf = std::max(Lf, k.L);
+  const double h = 1.0 / double(g->nb << Lf);
+  *dt = cfl * h / usum(*vel);
+  return MR_OK;
+}
+
+mr_status mr_block_meta(const mr_grid* g, int64_t n_cap, int64_t* n, int32_t* level, int32_t* ijk) {
+  if (!g || !n) return fail(MR_EINVAL, "null argument");
+  *n = int64_t(g->leaves.size());
+  if (!level && !ijk) return MR_OK;
+  if (n_cap < *n) return fail(MR_EINVAL, "n_cap smaller than the leaf count");
+  for (size_t b = 0; b < g->leaves.size(); ++b) {
+    if (level) level[b] = g->leaves[b].L;
+    if (ijk) {
+      ijk[3 * b] = g->leaves[b].i;
+      ijk[3 * b + 1] = g->leaves[b].j;
+      ijk[3 * b + 2] = g->leaves[b].k;
+    }
+  }
+  return MR_OK;
+}
+
+mr_status mr_field_get(mr_grid* g, int32_t field, void* host, size_t bytes) {
+  if (!g || !host || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
+  const size_t want = g->leaves.size() * size_t(g->nb * g->nb * g->nb) * g->esz;
+  if (bytes != want) return fail(MR_EINVAL, "size mismatch: expected " + std::to_string(want));
+  HIPCHK(hipMemcpyAsync(host, g->fields[field].p, bytes, hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  return MR_OK;
+}
+
+mr_status mr_field_set(mr_grid* g, int32_t field, const void* host, size_t bytes) {
+  if (!g || !host || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
+  const size_t want = g->leaves.size() * size_t(g->nb * g->nb * g->nb) * g->esz;
+  if (bytes != want) return fail(MR_EINVAL, "size mismatch: expected " + std::to_string(want));
+  HIPCHK(hipMemcpyAsync(g->fields[field].p, host, bytes, hipMemcpyHostToDevice, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  return MR_OK;
+}
+
+mr_status mr_field_ptr(mr_grid* g, int32_t field, void** dev_ptr) {
+  if (!g || !dev_ptr || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
+  *dev_ptr = g->fields[field].p;
+  return MR_OK;
+}
+
+mr_status mr_moments(mr_grid* g, int32_t field, double out[4]) {
+  if (!g || !out || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
+  const double z[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(g->d_mom.p, z, sizeof(z), hipMemcpyHostToDevice, g->stream));
+  AnyView v = anyview(g, g->fields[field].p);
+  launch_moments(g->f32, v.raw, static_cast<double*>(g->d_mom.p), g->stream);
+  HIPCHK(hipMemcpyAsync(out, g->d_mom.p, 4 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  return MR_OK;
+}
+
+mr_status mr_prof_enable(mr_grid* g, int32_t on) {
+  if (!g) return fail(MR_EINVAL, "null grid");
+  (void)hipStreamSynchronize(g->stream);
+  for (auto& r : g->prof.recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g->prof.recs.clear();
+  g->prof.on = on != 0;
+  return MR_OK;
+}
+
+mr_status mr_prof_read(mr_grid* g, const char* kernel, double* total_ms, int64_t* launches,
+                       int64_t* points_per_launch) {
+  if (!g || !kernel || !total_ms || !launches) return fail(MR_EINVAL, "null argument");
+  int fam = -1;
+  for (int f = 0; f < 4; ++f)
+    if (std::strcmp(kernel, kFam[f]) == 0) fam = f;
+  if (fam < 0) return fail(MR_EINVAL, "unknown kernel family");
+  HIPCHK(hipStreamSynchronize(g->stream));
+  double ms = 0;
+  int64_t cnt = 0;
+  for (auto& r : g->prof.recs) {
+    if (r.fam != fam) continue;
+    float t = 0;
+    HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+    ms += t;
+    ++cnt;
+  }
+  *total_ms = ms;
+  *launches = cnt;
+  if (points_per_launch) *points_per_launch = g->prof.points[fam];
+  return MR_OK;
+}
+
+mr_status mr_tree_stats(const mr_grid* g, int64_t out[5]) {
+  if (!g || !out) return fail(MR_EINVAL, "null argument");
+  int lo = 99, hi = -1;
+  for (const Key& k : g->leaves) {
+    lo = std::min(lo, k.L);
+    hi = std::max(hi, k.L);
+  }
+  out[0] = int64_t(g->leaves.size());
+  out[1] = g->stage.out_points;
+  int64_t subs = 0;
+  for (const GItem& it : g->stage.g) subs += it.mode == 0;
+  out[2] = subs;
+  out[3] = hi;
+  out[4] = lo;
+  return MR_OK;
+}
+
+}  // extern "C"

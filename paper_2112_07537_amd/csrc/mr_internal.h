@@ -1,0 +1,137 @@
+// Internal declarations shared by the host driver (mr_grid.cpp) and the HIP
+// kernels (mr_device.hip).  Not part of the public ABI (include/mr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mr {
+
+// Zero-detail refinement of a box (coarse-extension assumption, section
+// 2.2.2): the tensor Deslauriers-Dubuc refinement of the level-(Lb-1) samples
+// around a box of level-Lb points, Lb = level(blk) + up.  mode 0 writes the
+// substituted points of field[blk] (section 2.2.4); mode 1 writes the whole box
+// into a patch (c->f ghosts) or into scratch (fine view for a restriction).
+struct GItem {
+  int32_t blk;      // block whose owner map resolves the samples
+  int32_t up;       // 0: box at blk's level; 1: box one level finer
+  int32_t mode;     // 0: substitution into field[blk]; 1: box into out buffer
+  int32_t sel;      // mode 0: bits 0..2 = axes facing the coarser leaf,
+                    //         bit 3 = lifted wavelet (every non-all-even point)
+  int32_t lo[3];    // box [lo, hi) in coordinates relative to blk's origin
+  int32_t hi[3];    //   scaled to the box level
+  int32_t rlo[3];   // mode 1: origin and extent of the output array
+  int32_t rsz[3];
+  int32_t buf;      // mode 1: 0 = patch buffer, 1 = scratch buffer
+  int32_t pad;
+  int64_t off;      // mode 1: element offset of the output array
+};
+
+// Restriction of finer data to coarse ghost points (f->c, ghosting Part 2):
+// [H^a]^3 of the level-(L+1) view around each level-L point of a box of
+// block C's ghost region.  Samples held by coarser leaves come from a fine
+// view box computed by a GItem with up = 1 into scratch.
+struct RItem {
+  int32_t blk;      // coarse block C
+  int32_t lo[3];    // box of C-level points, relative to C's origin
+  int32_t hi[3];
+  int32_t rlo[3];   // patch region origin / extent for output indexing
+  int32_t rsz[3];
+  int32_t glo[3];   // fine view box (level L+1, relative to 2*origin(C))
+  int32_t gsz[3];   //   gsz = 0: no coarser-held samples
+  int32_t pad;
+  int64_t off;      // patch offset
+  int64_t goff;     // scratch offset of the fine view
+};
+
+// One separable pass of a box operation used by adaptation (refine, coarsen,
+// update): out[box] = sum_o w(o) in[p + o*axis], where the 1D filter depends
+// on the parity of the output coordinate along `axis`.
+struct PItem {
+  int32_t src_blk;  // block whose ext field / owner map the pass reads
+  int32_t dst_blk;  // destination block in the destination field array
+  int32_t lo[3];    // output box (relative coordinates of the pass output)
+  int32_t hi[3];
+  int32_t ilo[3];   // scratch input box origin / extent (src_mode 1)
+  int32_t isz[3];
+  int32_t dlo[3];   // field destination: block-local = output - dlo
+  int32_t pad;
+  int64_t in_off;   // scratch offset of the input box
+  int64_t out_off;  // scratch offset of the output box (dst_mode 0)
+};
+
+enum Filter1D : int32_t {
+  F_REFINE = 0,     // zero-detail synthesis (DD at odd, copy at even)
+  F_RESTRICT = 1,   // H^a at even fine positions (output at coarse points)
+  F_SYNTH = 2,      // J^s / K^s synthesis of an interleaved array
+  F_ANALYSIS = 3    // H^a / G^a analysis (interleaved output)
+};
+
+// Device view of the grid.
+template <typename T>
+struct DevGrid {
+  int32_t nb;
+  int32_t nblk;
+  const int32_t* lev;    // [nblk]
+  const int32_t* ijk;    // [3*nblk]
+  const int32_t* cmap;   // [64*nblk] leaf id per half-block cell of the
+                         //   4x4x4 cells covering [-nb/2, 3nb/2)^3
+  const int64_t* poff;   // [27*nblk] patch offset per region, -1 if none
+  T* field;              // [nblk * nb^3]
+  T* patch;
+  T* scratch;
+  int32_t dw;            // allocated depth of every patch region
+  int32_t* err;          // device error counter (unsupported geometry)
+};
+
+struct VelDev {
+  int32_t kind;
+  double p[8];
+};
+
+struct IcDev {
+  int32_t kind;
+  int32_t n;
+  const double* params;  // device pointer
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `s`; T is float or double selected by `f32`.
+struct Wavelet {
+  int32_t N, Nt;
+};
+
+void launch_gview(bool f32, const void* dg, Wavelet w, const GItem* items, int n_items,
+                  int lds_bytes, hipStream_t s);
+void launch_rview(bool f32, const void* dg, Wavelet w, const RItem* items, int n_items,
+                  int lds_bytes, hipStream_t s);
+// RK3 stage: out = a*un + b*(y + dt*rhs(y)); stage 0 ignores un.
+void launch_rhs(bool f32, const void* dg_y, const void* un, void* out, int fd_order, int depth,
+                double a_un, double b_y, double dt, const VelDev& vel, int first_blk,
+                int n_blk, hipStream_t s);
+// Details: per-block band maxima (27 per block, FP64), optional full detail
+// array of selected blocks (det_slot[b] >= 0) into det_out.
+void launch_details(bool f32, const void* dg, Wavelet w, int ef, int eb, double* bands,
+                    const int32_t* det_slot, double* det_out, int first_blk, int n_blk,
+                    hipStream_t s);
+void launch_combine(const void* dg_any, const double* bands, int detail_ext, double* norms,
+                    int n_blk, hipStream_t s);
+void launch_sample_ic(bool f32, const void* dg, const IcDev& ic, hipStream_t s);
+void launch_moments(bool f32, const void* dg, double* out4, hipStream_t s);
+void launch_gather_ext(bool f32, const void* dg, int depth, int64_t b0, int64_t nblk, void* out,
+                       hipStream_t s);
+void launch_copy_blocks(bool f32, const void* src, void* dst, const int32_t* pairs, int n_pairs,
+                        int nb, hipStream_t s);
+void launch_fill(bool f32, void* dst, size_t n, hipStream_t s);
+// src_mode: 0 gather the ext field of src_blk, 1 FP64 scratch box (din),
+// 2 discarded details (det, det_slot per old block); dst_mode: 0 FP64 scratch
+// box (dout), 1 store into dst field block, 2 subtract from dst field block
+// (block-local coordinates = output - dlo).
+void launch_pass(bool f32, const void* dg, Wavelet w, int filter, int axis, int src_mode,
+                 int dst_mode, const PItem* items, int n_items, const double* din, double* dout,
+                 const double* det, const int32_t* det_slot, void* dst, hipStream_t s);
+const char* device_error(hipError_t e);
+
+}  // namespace mr

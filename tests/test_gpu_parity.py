@@ -1,0 +1,242 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (from the required precision contract): FP64 within 1e-12 of
+max|phi|, FP32 within 1e-5 of max|phi| per operation started from the same
+state; octree leaf sets identical.
+"""
+import numpy as np
+import pytest
+
+from oracle import grid as og
+from paper_2112_07537_amd import mr
+from paper_2112_07537_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def two_level(nb, Lc, pattern):
+    keys = []
+    n = 1 << Lc
+    for k in range(n):
+        for j in range(n):
+            for i in range(n):
+                if pattern(i, j, k):
+                    for c in range(8):
+                        keys.append((Lc + 1, 2 * i + (c & 1), 2 * j + ((c >> 1) & 1),
+                                     2 * k + ((c >> 2) & 1)))
+                else:
+                    keys.append((Lc, i, j, k))
+    return keys
+
+
+def oracle_from_gpu(g, N, Nt, fd, **kw):
+    """Oracle grid holding exactly the GPU's tree and field (upcast)."""
+    meta = g.block_meta()
+    data = g.field_get().astype(np.float64)
+    o = og.Grid(g.nb, N, Nt, fd_order=fd, **kw)
+    keys = [tuple(int(v) for v in m) for m in meta]
+    o.set_tree(keys)
+    for b, k in enumerate(keys):
+        o.blocks[k] = data[b].copy()
+    return o, keys
+
+
+def rand_field(n, nb, seed, dtype):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, nb, nb, nb)).astype(dtype)
+
+
+def smooth_field(keys, nb):
+    f = wl.ic_function(("gauss", wl.gauss_params([(0.45, 0.5, 0.55)], [0.2], [1.0])))
+    out = []
+    for (L, i, j, k) in keys:
+        den = float(nb << L)
+        x = (i * nb + np.arange(nb)) / den
+        y = (j * nb + np.arange(nb)) / den
+        z = (k * nb + np.arange(nb)) / den
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+        out.append(f(X, Y, Z))
+    return np.array(out)
+
+
+CASES = [(16, 2, 0, 4), (16, 4, 0, 4), (16, 4, 2, 4), (16, 2, 2, 4), (24, 6, 2, 6), (24, 6, 0, 6)]
+
+
+def make(nb, N, Nt, fd, prec="f64", keys=None, **kw):
+    g = mr.Grid(nb, N, Nt, fd_order=fd, level_min=0, level_max=8, prec=prec,
+                max_blocks=4096, **kw)
+    if keys is not None:
+        g.set_tree(keys)
+    return g
+
+
+def tree_for(nb):
+    # coarse level 1 with three refined octants: face, edge and corner jumps
+    return two_level(nb, 1, lambda i, j, k: (i, j, k) in ((0, 0, 0), (1, 1, 0), (0, 1, 1)))
+
+
+@pytest.mark.parametrize("nb,N,Nt,fd", CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ghost_parity(nb, N, Nt, fd, prec):
+    dtype = np.float32 if prec == "f32" else np.float64
+    g = make(nb, N, Nt, fd, prec, tree_for(nb))
+    n = g.n_blocks()
+    f = rand_field(n, nb, 3 + N + Nt, dtype)
+    g.field_set(f)
+    o, keys = oracle_from_gpu(g, N, Nt, fd)
+    o.substitute()
+    scale = np.abs(f).max()
+    for depth in sorted({fd // 2, 0}):
+        d = depth or fd // 2
+        g.ghost(depth=d)
+        ext = g.ghost_get(d)
+        for b, k in enumerate(keys):
+            ref = o.ghost_block(k, d)
+            err = np.abs(ext[b].astype(np.float64) - ref).max()
+            assert err <= TOL[prec] * scale * 4, (k, d, err)
+    # substituted field itself
+    got = g.field_get().astype(np.float64)
+    for b, k in enumerate(keys):
+        assert np.abs(got[b] - o.blocks[k]).max() <= TOL[prec] * scale * 4
+
+
+@pytest.mark.parametrize("nb,N,Nt,fd", [(16, 4, 2, 4), (24, 6, 2, 6), (16, 4, 0, 4)])
+def test_wide_ghost_parity(nb, N, Nt, fd):
+    g = make(nb, N, Nt, fd, "f64", tree_for(nb))
+    n = g.n_blocks()
+    f = rand_field(n, nb, 5, np.float64)
+    g.field_set(f)
+    o, keys = oracle_from_gpu(g, N, Nt, fd)
+    o.substitute()
+    H = N if Nt else 0
+    Dw = max(fd // 2, max(H, N - 2), max(H - 1, N - 1), N // 2, H)
+    g.ghost(depth=Dw)
+    ext = g.ghost_get(Dw)
+    scale = np.abs(f).max()
+    for b, k in enumerate(keys):
+        ref = o.ghost_block(k, Dw)
+        assert np.abs(ext[b] - ref).max() <= 1e-12 * scale * 4, k
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("nb,N,Nt,fd", [(16, 4, 0, 4), (16, 4, 2, 4), (24, 6, 2, 6)])
+def test_rk3_step_parity(nb, N, Nt, fd, prec):
+    dtype = np.float32 if prec == "f32" else np.float64
+    keys = tree_for(nb)
+    g = make(nb, N, Nt, fd, prec, keys)
+    meta = [tuple(int(v) for v in m) for m in g.block_meta()]
+    g.field_set(smooth_field(meta, nb).astype(dtype))
+    o, keys = oracle_from_gpu(g, N, Nt, fd)
+    for vel in (("const", (1.0, 0.5, 0.25)), ("rotating", (0.5, 0.5, 0.2)), ("shear", ())):
+        v = mr.velocity(vel[0], *vel[1])
+        dt = g.cfl_dt(v, 0.5)
+        g.rk3_step(dt, v)
+        o.rk3_step(dt, vel)
+        got = g.field_get().astype(np.float64)
+        scale = max(np.abs(b).max() for b in o.blocks.values())
+        err = max(np.abs(got[b] - o.blocks[k]).max() for b, k in enumerate(keys))
+        assert err <= TOL[prec] * scale, (vel[0], err)
+        # restart both from the GPU state so FP32 errors do not accumulate
+        for b, k in enumerate(keys):
+            o.blocks[k] = got[b].copy()
+
+
+def test_c1_rk3_and_details():
+    cfg = wl.c1()
+    g = mr.Grid(cfg["nb"], cfg["N"], cfg["Nt"], fd_order=cfg["fd"], level_min=1, level_max=1,
+                prec="f64", max_blocks=64)
+    g.sample_ic(*cfg["ic"])
+    o, keys = oracle_from_gpu(g, cfg["N"], cfg["Nt"], cfg["fd"])
+    f_ref = wl.ic_function(cfg["ic"])
+    o.sample(f_ref)
+    got = g.field_get()
+    for b, k in enumerate(keys):
+        assert np.abs(got[b] - o.blocks[k]).max() <= 1e-15
+    v = mr.velocity(*cfg["vel"][0:1], *cfg["vel"][1])
+    dt = g.cfl_dt(v, cfg["cfl"])
+    assert abs(dt - 0.5 * (1.0 / 32) / 1.75) < 1e-18
+    g.rk3_step(dt, v)
+    o.rk3_step(dt, cfg["vel"])
+    got = g.field_get()
+    err = max(np.abs(got[b] - o.blocks[k]).max() for b, k in enumerate(keys))
+    assert err <= 1e-12
+    nrm = g.details()
+    onrm = o.norms()
+    for b, k in enumerate(keys):
+        assert abs(nrm[b] - onrm[k]) <= 1e-12 * max(1e-300, abs(onrm[k])) + 1e-15
+
+
+@pytest.mark.parametrize("ext", [0, 1])
+@pytest.mark.parametrize("nb,N,Nt,fd", CASES)
+def test_details_parity(nb, N, Nt, fd, ext):
+    g = make(nb, N, Nt, fd, "f64", tree_for(nb), detail_ext=ext)
+    meta = [tuple(int(v) for v in m) for m in g.block_meta()]
+    g.field_set(smooth_field(meta, nb) + 1e-3 * rand_field(len(meta), nb, 9, np.float64))
+    o, keys = oracle_from_gpu(g, N, Nt, fd, detail_ext=ext)
+    nrm = g.details()
+    o.substitute()
+    onrm = o.norms()
+    for b, k in enumerate(keys):
+        assert abs(nrm[b] - onrm[k]) <= 1e-12 * abs(onrm[k]) + 1e-16, (k, nrm[b], onrm[k])
+
+
+def test_moments_parity():
+    g = make(16, 4, 2, 4, "f64", tree_for(16))
+    meta = [tuple(int(v) for v in m) for m in g.block_meta()]
+    g.field_set(smooth_field(meta, 16))
+    o, keys = oracle_from_gpu(g, 4, 2, 4)
+    m = g.moments()
+    mo = o.moments()
+    assert np.abs(m - mo).max() <= 1e-13 * np.abs(mo).max()
+
+
+@pytest.mark.parametrize("nb,N,Nt,fd", [(16, 4, 2, 4), (16, 4, 0, 4), (24, 6, 2, 6)])
+def test_adapt_apply_parity(nb, N, Nt, fd):
+    """One adaptation iteration from a given tree and field: refine and
+    coarsen decisions, interpolated values and the update step."""
+    keys = two_level(nb, 1, lambda i, j, k: (i, j, k) in ((0, 0, 0), (1, 1, 1)))
+    g = mr.Grid(nb, N, Nt, fd_order=fd, level_min=1, level_max=3, prec="f64",
+                eps_refine=2e-2, eps_coarsen=2e-4, max_blocks=4096)
+    g.set_tree(keys)
+    meta = [tuple(int(v) for v in m) for m in g.block_meta()]
+    f = wl.ic_function(("gauss", wl.gauss_params([(0.3, 0.35, 0.3)], [0.09], [1.0])))
+    data = []
+    for (L, i, j, k) in meta:
+        den = float(nb << L)
+        x = (i * nb + np.arange(nb)) / den
+        y = (j * nb + np.arange(nb)) / den
+        z = (k * nb + np.arange(nb)) / den
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+        data.append(f(X, Y, Z))
+    g.field_set(np.array(data))
+    o, _ = oracle_from_gpu(g, N, Nt, fd, level_min=1, level_max=3, eps_refine=2e-2,
+                           eps_coarsen=2e-4)
+    st = g.adapt(max_iter=1)
+    o_st = o.adapt(max_iter=1)
+    assert st.refined == o_st["refined"] and st.coarsened == o_st["coarsened"]
+    assert st.refined + st.coarsened > 0
+    meta2 = [tuple(int(v) for v in m) for m in g.block_meta()]
+    assert sorted(meta2) == o.keys()
+    got = g.field_get()
+    scale = max(np.abs(b).max() for b in o.blocks.values())
+    for b, k in enumerate(meta2):
+        assert np.abs(got[b] - o.blocks[k]).max() <= 1e-12 * scale * 4, k
+
+
+def test_abi_errors_on_gpu():
+    with pytest.raises(mr.MRError):
+        mr.Grid(16, 5, 0)
+    g = make(16, 4, 2, 4)
+    with pytest.raises(mr.MRError):
+        g.set_tree([(1, 0, 0, 0)])           # does not tile the cube
+    bad = two_level(16, 1, lambda i, j, k: True)
+    bad = [k for k in bad if not (k[0] == 2 and k[1:] == (0, 0, 0))]
+    bad += [(3, c & 1, (c >> 1) & 1, (c >> 2) & 1) for c in range(8)]
+    g.set_tree(bad)                          # 2:1 holds (levels 2 and 3)
+    too_deep = [k for k in two_level(16, 1, lambda i, j, k: (i, j, k) == (0, 0, 0))
+                if k != (2, 0, 0, 0)]
+    too_deep += [(3, c & 1, (c >> 1) & 1, (c >> 2) & 1) for c in range(8)]
+    with pytest.raises(mr.MRError):
+        g.set_tree(too_deep)                 # level 3 next to level 1
