@@ -1,0 +1,212 @@
+"""Benchmark of the multiresolution hot path on one MI355X.
+
+A step is one SSP-RK3 step of the whole grid (three stages, each a ghost
+reconstruction -- substitution, c->f and f->c patches -- plus the fused FD
+advection + RK combine) followed by one detail pass (wide ghost
+reconstruction, FP64 forward transform, per-block norms).  The timed region
+starts with the field resident in HBM.  Adaptation is timed in a second loop
+(every `adapt_every` steps) and reported separately.
+
+Prints one JSON line.  Progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2112_07537_amd import mr  # noqa: E402
+from paper_2112_07537_amd import workloads as wl  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "RK3-step grid points/s (ghost+details+RHS) & % HBM peak, FP32-batched vs FP64-plain"
+
+
+def log(*a):
+    print("[bench %.1fs]" % (time.time() - T0), *a, file=sys.stderr, flush=True)
+
+
+T0 = time.time()
+
+
+def make_grid(cfg, prec=None, exec_mode=0, max_blocks=150000):
+    g = mr.Grid(cfg["nb"], cfg["N"], cfg["Nt"], fd_order=cfg["fd"], level_min=cfg["level_min"],
+                level_max=cfg["level_max"], prec=prec or cfg["prec"],
+                eps_refine=cfg["eps_refine"], eps_coarsen=cfg["eps_coarsen"],
+                exec_mode=exec_mode, max_blocks=max_blocks)
+    if cfg.get("tree"):
+        g.set_tree(wl.geometric_tree())
+        g.sample_ic(*cfg["ic"])
+    else:
+        st = g.init_ic(*cfg["ic"])
+        log("init: %d leaves, %d refine / %d coarsen in %d adapt iterations" %
+            (g.n_blocks(), st.refined, st.coarsened, st.iters))
+    return g
+
+
+def timed_steps(g, cfg, steps, warmup, adapt_every=0):
+    kind, p = wl.velocity_spec(cfg["vel"])
+    vel = mr.velocity(kind, *p)
+    dt = g.cfl_dt(vel, cfg["cfl"])
+    for _ in range(warmup):
+        g.rk3_step(dt, vel)
+        g.details_async()
+    g.sync()
+    t_adapt = 0.0
+    n_adapt = 0
+    points = 0
+    t0 = time.perf_counter()
+    for s in range(steps):
+        points += g.n_blocks() * cfg["nb"] ** 3
+        g.rk3_step(dt, vel)
+        g.details_async()
+        if adapt_every and (s + 1) % adapt_every == 0:
+            ta = time.perf_counter()
+            g.adapt()
+            t_adapt += time.perf_counter() - ta
+            n_adapt += 1
+            dt = g.cfl_dt(vel, cfg["cfl"])
+    g.sync()
+    t = time.perf_counter() - t0
+    return t, points, t_adapt, n_adapt
+
+
+def cpu_baseline(g, cfg, n_sample=12, seed=1234):
+    """The FP64 oracle timed on a seeded sample of the same grid: per sampled
+    block, three stages of (substitution + ghost reconstruction + RHS) and one
+    detail transform, computed from the GPU's current state."""
+    from oracle import grid as og
+    meta = [tuple(int(v) for v in m) for m in g.block_meta()]
+    data = g.field_get()
+    o = og.Grid(cfg["nb"], cfg["N"], cfg["Nt"], fd_order=cfg["fd"], level_min=cfg["level_min"],
+                level_max=cfg["level_max"], eps_refine=cfg["eps_refine"],
+                eps_coarsen=cfg["eps_coarsen"])
+    o.blocks = {k: data[b] for b, k in enumerate(meta)}  # upcast lazily below
+    o._index()
+    rng = np.random.default_rng(seed)
+    sample = [meta[i] for i in rng.choice(len(meta), size=min(n_sample, len(meta)), replace=False)]
+    for k in set(sample):
+        o.blocks[k] = o.blocks[k].astype(np.float64)
+    kind, p = wl.velocity_spec(cfg["vel"])
+    vel = (kind, p)
+    t0 = time.perf_counter()
+    for k in sample:
+        for _ in range(3):
+            for key, z, y, x, v in o.substitution_writes(k):
+                o.blocks[key][z, y, x] = v
+            o.rhs_block(k, vel)
+        o.block_details(k)
+    t = time.perf_counter() - t0
+    pts = len(sample) * cfg["nb"] ** 3
+    return {"value": pts / t, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": "%d seeded blocks of the %s grid (%d^3 points each): 3 x (substitution + "
+                      "ghost + RHS) + 1 detail transform per block, FP64 numpy, %.1f s" %
+                      (len(sample), cfg["name"], cfg["nb"], t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c5")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--eps-refine", type=float, default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the whole octree on a single "
+              "MI355X and has no multi-GPU path (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    cfg = getattr(wl, args.config)(**({"eps_refine": args.eps_refine} if args.eps_refine else {}))
+    log("config", cfg["name"])
+    g = make_grid(cfg)
+    n_blocks = g.n_blocks()
+    ts = g.tree_stats()
+    log("grid: %d leaves, levels %d..%d, %.3g points" %
+        (n_blocks, ts[4], ts[3], n_blocks * cfg["nb"] ** 3))
+
+    # -- headline: batched path, per-kernel HIP events around the launches
+    g.prof_enable(True)
+    t, points, _, _ = timed_steps(g, cfg, args.steps, args.warmup)
+    value = points / t
+    ms = 1e3 * t / args.steps
+    log("batched %s: %.3f ms/step, %.4g points/s" % (cfg["prec"], ms, value))
+    rhs_ms, rhs_n, rhs_pts = g.prof_read("rhs")
+    det_ms, det_n, det_pts = g.prof_read("details")
+    gr_ms, gr_n, _ = g.prof_read("ghost_refine")
+    gx_ms, gx_n, _ = g.prof_read("ghost_restrict")
+    g.prof_enable(False)
+    esz = 4 if cfg["prec"] == "f32" else 8
+    # algorithmic words per point of the three RK stages: (2 + 3 + 3)
+    rhs_bytes = (2 + 3 + 3) / 3.0 * esz * rhs_pts * rhs_n
+    achieved = rhs_bytes / (rhs_ms * 1e-3) / 1e9 if rhs_ms > 0 else 0.0
+    det_gbs = esz * det_pts * det_n / (det_ms * 1e-3) / 1e9 if det_ms > 0 else 0.0
+    step_bytes = 9 * esz * n_blocks * cfg["nb"] ** 3
+    step_frac = step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+    breakdown = {k: round(v / args.steps, 4) for k, v in
+                 (("rhs_ms", rhs_ms), ("details_ms", det_ms), ("ghost_refine_ms", gr_ms),
+                  ("ghost_restrict_ms", gx_ms))}
+
+    # -- adaptation amortised (second loop, same grid)
+    extra = {}
+    if cfg.get("adapt_every"):
+        ta_t, ta_pts, t_adapt, n_adapt = timed_steps(g, cfg, max(args.steps, cfg["adapt_every"]),
+                                                     0, adapt_every=cfg["adapt_every"])
+        extra["with_adapt_points_per_s"] = ta_pts / ta_t
+        extra["adapt_ms_each"] = 1e3 * t_adapt / max(1, n_adapt)
+        extra["adapt_every"] = cfg["adapt_every"]
+        log("with adapt every %d: %.4g points/s, %.1f ms per adaptation, %d leaves" %
+            (cfg["adapt_every"], extra["with_adapt_points_per_s"], extra["adapt_ms_each"],
+             g.n_blocks()))
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle sample)")
+        cpu = cpu_baseline(g, cfg)
+        log("cpu: %.4g points/s" % cpu["value"])
+    g.close()
+
+    # -- FP64 plain path (one launch per block per operation, no graph)
+    if not args.no_plain:
+        log("fp64 plain path")
+        gp = make_grid(cfg, prec="f64", exec_mode=1)
+        tp, pp, _, _ = timed_steps(gp, cfg, args.plain_steps, 1)
+        extra["fp64_plain_points_per_s"] = pp / tp
+        extra["speedup_vs_fp64_plain"] = value / extra["fp64_plain_points_per_s"]
+        extra["fp64_plain_leaves"] = gp.n_blocks()
+        log("fp64 plain: %.4g points/s" % extra["fp64_plain_points_per_s"])
+        gp.close()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": cfg["prec"], "data": "synthetic",
+        "config": {"workload": cfg["name"], "leaves": n_blocks, "points": n_blocks * cfg["nb"] ** 3,
+                   "levels": [int(ts[4]), int(ts[3])], "nb": cfg["nb"],
+                   "wavelet": "%d.%d" % (cfg["N"], cfg["Nt"]), "fd_order": cfg["fd"],
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_rhs (FD advection + SSP-RK3 stage)",
+                     "bytes_per_launch": rhs_bytes / max(1, rhs_n),
+                     "avg_launch_ms": rhs_ms / max(1, rhs_n)},
+        "step_hbm_frac_algorithmic": step_frac,
+        "details_kernel_gbs": det_gbs,
+        "per_step_kernel_ms": breakdown,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

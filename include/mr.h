@@ -141,7 +141,9 @@ mr_status mr_ghost_get(mr_grid* g, int32_t field, int32_t depth, int64_t b0,
 
 /* Block criterion of section 2.2.5: ghost reconstruction, one-level forward
  * transform (x, y, z), per-block max |gamma| (FP64).  norms: n_blocks
- * doubles, host (on_device = 0, synchronises) or device (on_device = 1). */
+ * doubles, host (on_device = 0, synchronises) or device (on_device = 1);
+ * with on_device = 1, norms may be NULL: the norms stay in the library's
+ * device buffer (asynchronous). */
 mr_status mr_details(mr_grid* g, int32_t field, double* norms, int32_t on_device);
 
 /* Iterative adaptation (adaptation supplement): criterion, flags, policy
@@ -186,10 +188,15 @@ mr_status mr_prof_enable(mr_grid* g, int32_t on);
 mr_status mr_prof_read(mr_grid* g, const char* kernel, double* total_ms, int64_t* launches,
                        int64_t* points_per_launch);
 
-/* Counts describing the current tree: out[0] = leaves, out[1] = cross-level
- * ghost patch values at stencil depth, out[2] = substituted-slab work items,
- * out[3] = finest level present, out[4] = coarsest level present. */
-mr_status mr_tree_stats(const mr_grid* g, int64_t out[5]);
+/* Counts describing the current tree: out[0] = leaves, out[1] = ghost values
+ * produced per stencil-depth reconstruction, out[2] = substitution work
+ * items, out[3] = finest level, out[4] = coarsest level, out[5] = refinement
+ * work items, out[6] = restriction work items, out[7] / out[8] = their LDS
+ * bytes, out[9] = allocated patch values. */
+mr_status mr_tree_stats(const mr_grid* g, int64_t out[10]);
+
+/* Wait until all work issued on the grid's stream has finished. */
+mr_status mr_sync(mr_grid* g);
 
 const char* mr_last_error(void);
 

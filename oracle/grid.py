@@ -267,6 +267,37 @@ class Grid:
                 rng.append((0, N) if d[a] < 0 else (nb - N + 1, nb))
         return rng
 
+    def substitution_writes(self, key):
+        """Points of block ``key`` overwritten by the substitution step of
+        section 2.2.4 / 2.3 (see ``substitute``) and their new values."""
+        L = key[0]
+        writes = []
+        for d in DIRS:
+            if self.neighbor_level(key, d) >= L:
+                continue
+            rng = self.substitution_slab(d)
+            lo = np.array([r[0] for r in rng])
+            shape = np.array([r[1] - r[0] for r in rng])
+            if (shape <= 0).any():
+                continue
+            G = self.refine_box(L, self.origin(key) + lo, shape)
+            x, y, z = self._box(lo, shape)
+            par = [x % 2, y % 2, z % 2]
+            if self.Nt > 0:
+                sel = (par[0] + par[1] + par[2]) > 0
+            else:
+                sel = np.ones(x.shape, bool)
+                tang_odd = np.zeros(x.shape, bool)
+                for a in range(3):
+                    if d[a] != 0:
+                        sel &= par[a] == 0
+                    else:
+                        tang_odd |= par[a] == 1
+                sel &= tang_odd
+            if sel.any():
+                writes.append((key, z[sel], y[sel], x[sel], G[sel]))
+        return writes
+
     def substitute(self):
         """Substitution step of section 2.2.4 / 2.3 on every fine block next to
         a coarser leaf: each selected point gets the tensor-product
@@ -277,31 +308,7 @@ class Grid:
         depend on the order in which blocks or slabs are visited."""
         writes = []
         for key in sorted(self.blocks):
-            L = key[0]
-            for d in DIRS:
-                if self.neighbor_level(key, d) >= L:
-                    continue
-                rng = self.substitution_slab(d)
-                lo = np.array([r[0] for r in rng])
-                shape = np.array([r[1] - r[0] for r in rng])
-                if (shape <= 0).any():
-                    continue
-                G = self.refine_box(L, self.origin(key) + lo, shape)
-                x, y, z = self._box(lo, shape)
-                par = [x % 2, y % 2, z % 2]
-                if self.Nt > 0:
-                    sel = (par[0] + par[1] + par[2]) > 0
-                else:
-                    sel = np.ones(x.shape, bool)
-                    tang_odd = np.zeros(x.shape, bool)
-                    for a in range(3):
-                        if d[a] != 0:
-                            sel &= par[a] == 0
-                        else:
-                            tang_odd |= par[a] == 1
-                    sel &= tang_odd
-                if sel.any():
-                    writes.append((key, z[sel], y[sel], x[sel], G[sel]))
+            writes += self.substitution_writes(key)
         for key, z, y, x, v in writes:
             self.blocks[key][z, y, x] = v
         return len(writes)

@@ -11,9 +11,27 @@
 #include <cmath>
 #include <cstdint>
 
+#include <hip/hip_ext.h>
+
 #include "mr_internal.h"
 
 namespace mr {
+
+// Optional events recorded by the runtime exactly at the start and end of
+// the next launch (hipExtLaunchKernel), used by the kernel timers.
+static hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+void set_launch_events(hipEvent_t a, hipEvent_t b) {
+  g_ev_start = a;
+  g_ev_stop = b;
+}
+#define MR_LAUNCH(kernel, grid, block, lds, stream, ...)                                  \
+  do {                                                                                    \
+    if (g_ev_start)                                                                       \
+      hipExtLaunchKernelGGL(kernel, grid, block, lds, stream, g_ev_start, g_ev_stop, 0,   \
+                            __VA_ARGS__);                                                 \
+    else                                                                                  \
+      hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);                  \
+  } while (0)
 
 // ------------------------------------------------------------------ filters
 // Deslauriers-Dubuc prediction of order N (K^s at the scaling positions):
@@ -203,175 +221,198 @@ __device__ __forceinline__ T refine_tap(const T* line, int stride, int p, int c0
   return acc;
 }
 
-template <typename T, int N, int NT>
+// Owner-map cells of block m cached in LDS: leaf id, level, origin at its
+// level.  Turns a sample lookup into LDS reads plus one global load.
+struct CellTab {
+  int32_t id[64], lev[64], ox[64], oy[64], oz[64];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_cells(const DevGrid<T>& g, int m, CellTab& ct) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    const int id = g.cmap[m * 64 + t];
+    ct.id[t] = id;
+    ct.lev[t] = g.lev[id];
+    ct.ox[t] = g.ijk[3 * id] * g.nb;
+    ct.oy[t] = g.ijk[3 * id + 1] * g.nb;
+    ct.oz[t] = g.ijk[3 * id + 2] * g.nb;
+  }
+}
+
+__device__ __forceinline__ int wrap1(int X, int W) {
+  X += (X < 0) ? W : 0;
+  X -= (X >= W) ? W : 0;
+  return X;
+}
+
+// Value at the level-L point p (relative to block m at level L, origin O) of
+// the leaf holding it, by injection; p must lie on that leaf's grid and in
+// the half-block shell [-NB/2, 3NB/2)^3 covered by the owner map.
+template <typename T, int NB>
+__device__ __forceinline__ T cell_value(const DevGrid<T>& g, const CellTab& ct, int L, int Ox,
+                                        int Oy, int Oz, int px, int py, int pz) {
+  constexpr int H = NB / 2;
+  const unsigned ux = unsigned(px + H), uy = unsigned(py + H), uz = unsigned(pz + H);
+  if (ux >= 4u * H || uy >= 4u * H || uz >= 4u * H) {
+    atomicAdd(g.err, 1);
+    return T(0);
+  }
+  const int c = ((uz / H) * 4 + uy / H) * 4 + ux / H;
+  const int W = NB << L;
+  int X = wrap1(Ox + px, W), Y = wrap1(Oy + py, W), Z = wrap1(Oz + pz, W);
+  const int l = ct.lev[c];
+  if (l > L) {
+    X <<= 1; Y <<= 1; Z <<= 1;
+  } else if (l < L) {
+    if ((X | Y | Z) & 1) {
+      atomicAdd(g.err, 1);
+      return T(0);
+    }
+    X >>= 1; Y >>= 1; Z >>= 1;
+  }
+  const unsigned lx = unsigned(X - ct.ox[c]), ly = unsigned(Y - ct.oy[c]), lz = unsigned(Z - ct.oz[c]);
+  if (lx >= unsigned(NB) || ly >= unsigned(NB) || lz >= unsigned(NB)) {
+    atomicAdd(g.err, 1);
+    return T(0);
+  }
+  return g.field[(int64_t)ct.id[c] * (NB * NB * NB) + (lz * NB + ly) * NB + lx];
+}
+
+// Row iteration helper: rows of a 2D index space (a, b) in [0,na) x [0,nb_),
+// visited with stride `step` starting at `start`, without divisions.
+struct RowIt {
+  int a, b, na;
+  __device__ __forceinline__ RowIt(int start, int na_) : na(na_) {
+    a = start % na_;
+    b = start / na_;
+  }
+  __device__ __forceinline__ void advance(int step) {
+    a += step;
+    while (a >= na) {
+      a -= na;
+      ++b;
+    }
+  }
+};
+
+// Flattened iteration over a 3D box [0,w0) x [0,w1) x [0,w2) with a fixed
+// thread stride, carrying the coordinates incrementally (no divisions in the
+// loop; the stride is decomposed once).
+struct Iter3 {
+  int x, y, z, w0, w1, sx, sy, sz;
+  __device__ __forceinline__ Iter3(int start, int step, int w0_, int w1_) : w0(w0_), w1(w1_) {
+    x = start % w0;
+    int t = start / w0;
+    y = t % w1;
+    z = t / w1;
+    sx = step % w0;
+    t = step / w0;
+    sy = t % w1;
+    sz = t / w1;
+  }
+  __device__ __forceinline__ void advance() {
+    x += sx;
+    y += sy;
+    z += sz;
+    if (x >= w0) {
+      x -= w0;
+      ++y;
+    }
+    if (y >= w1) {
+      y -= w1;
+      ++z;
+    }
+  }
+};
+
+// XCD-aware item order: workgroup i runs on XCD i % 8; give each XCD one
+// contiguous run of items (items are in Morton block order).
+__device__ __forceinline__ int xcd_item(int i, int n) {
+  if (n < 64) return i;
+  const int q = n >> 3, r = n & 7, x = i & 7, k = i >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
+template <typename T, int N, int NT, int NB>
 __global__ __launch_bounds__(256) void k_gview(DevGrid<T> g, const GItem* __restrict__ items) {
   extern __shared__ unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
-  const GItem it = items[blockIdx.x];
+  __shared__ CellTab ct;
+  const GItem it = items[xcd_item(blockIdx.x, gridDim.x)];
   const int m = it.blk;
+  load_cells(g, m, ct);
   const int L = g.lev[m];
   int clo[3], cs[3], fs[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    clo[a] = floordiv(it.lo[a], 2) - N / 2;
-    cs[a] = floordiv(it.hi[a] - 1, 2) + N / 2 + 1 - clo[a];
+    clo[a] = (it.lo[a] >> 1) - N / 2;
+    cs[a] = ((it.hi[a] - 1) >> 1) + N / 2 + 1 - clo[a];
     fs[a] = it.hi[a] - it.lo[a];
   }
-  T* S = lds;                              // [cs2][cs1][cs0]
-  T* T1 = S + cs[0] * cs[1] * cs[2];       // [cs2][cs1][fs0]
-  T* T2 = T1 + fs[0] * cs[1] * cs[2];      // [cs2][fs1][fs0]
-  const int nb = g.nb;
-  const int ox = g.ijk[3 * m] * nb, oy = g.ijk[3 * m + 1] * nb, oz = g.ijk[3 * m + 2] * nb;
-  // samples at level L + up - 1, i.e. level-L points p = c << (1 - up)
-  const int sh = 1 - it.up;
-  const int ns = cs[0] * cs[1] * cs[2];
-  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
-    const int cx = clo[0] + i % cs[0];
-    const int cy = clo[1] + (i / cs[0]) % cs[1];
-    const int cz = clo[2] + i / (cs[0] * cs[1]);
-    const int px = cx << sh, py = cy << sh, pz = cz << sh;
-    T v = T(0);
-    const int id = owner_id(g, m, 0, px, py, pz);
-    if (id >= 0 && !leaf_value(g, id, L, ox + px, oy + py, oz + pz, v)) atomicAdd(g.err, 1);
-    S[i] = v;
+  // S is dead once T1 is built, so T2 reuses its space
+  T* T1 = lds;                                                        // [cs2][cs1][fs0]
+  T* S = T1 + fs[0] * cs[1] * cs[2];                                  // [cs2][cs1][cs0]
+  T* T2 = S;                                                          // [cs2][fs1][fs0]
+  const int ox = g.ijk[3 * m] * NB, oy = g.ijk[3 * m + 1] * NB, oz = g.ijk[3 * m + 2] * NB;
+  const int nt = blockDim.x;
+  __syncthreads();
+  // coarse samples: level-(L-1) points c, i.e. level-L points p = 2c
+  {
+    const int n = cs[0] * cs[1] * cs[2];
+    Iter3 q(threadIdx.x, nt, cs[0], cs[1]);
+    for (int i = threadIdx.x; i < n; i += nt, q.advance())
+      S[i] = cell_value<T, NB>(g, ct, L, ox, oy, oz, 2 * (clo[0] + q.x), 2 * (clo[1] + q.y),
+                               2 * (clo[2] + q.z));
   }
   __syncthreads();
-  const int n1 = fs[0] * cs[1] * cs[2];
-  for (int i = threadIdx.x; i < n1; i += blockDim.x) {
-    const int fx = i % fs[0];
-    const int r = i / fs[0];   // (cz, cy) row
-    T1[i] = refine_tap<T, N>(S + r * cs[0], 1, it.lo[0] + fx, clo[0]);
+  {
+    const int n = fs[0] * cs[1] * cs[2];
+    Iter3 q(threadIdx.x, nt, fs[0], cs[1]);
+    for (int i = threadIdx.x; i < n; i += nt, q.advance())
+      T1[i] = refine_tap<T, N>(S + (q.z * cs[1] + q.y) * cs[0], 1, it.lo[0] + q.x, clo[0]);
   }
   __syncthreads();
-  const int n2 = fs[0] * fs[1] * cs[2];
-  for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-    const int fx = i % fs[0];
-    const int fy = (i / fs[0]) % fs[1];
-    const int cz = i / (fs[0] * fs[1]);
-    T2[i] = refine_tap<T, N>(T1 + cz * fs[0] * cs[1] + fx, fs[0], it.lo[1] + fy, clo[1]);
+  {
+    const int n = fs[0] * fs[1] * cs[2];
+    Iter3 q(threadIdx.x, nt, fs[0], fs[1]);
+    for (int i = threadIdx.x; i < n; i += nt, q.advance())
+      T2[i] = refine_tap<T, N>(T1 + q.z * fs[0] * cs[1] + q.x, fs[0], it.lo[1] + q.y, clo[1]);
   }
   __syncthreads();
-  const int n3 = fs[0] * fs[1] * fs[2];
-  const int64_t nb3 = (int64_t)nb * nb * nb;
-  for (int i = threadIdx.x; i < n3; i += blockDim.x) {
-    const int fx = i % fs[0];
-    const int fy = (i / fs[0]) % fs[1];
-    const int fz = i / (fs[0] * fs[1]);
-    const T v = refine_tap<T, N>(T2 + fy * fs[0] + fx, fs[0] * fs[1], it.lo[2] + fz, clo[2]);
-    const int x = it.lo[0] + fx, y = it.lo[1] + fy, z = it.lo[2] + fz;
-    if (it.mode == 0) {
-      const int par[3] = {x & 1, y & 1, z & 1};
-      bool take;
-      if (it.sel & 8) {
-        take = (par[0] | par[1] | par[2]) != 0;
-      } else {
-        take = true;
-        bool tang_odd = false;
+  constexpr int64_t nb3 = (int64_t)NB * NB * NB;
+  {
+    const int n = fs[0] * fs[1] * fs[2];
+    Iter3 q(threadIdx.x, nt, fs[0], fs[1]);
+    for (int i = threadIdx.x; i < n; i += nt, q.advance()) {
+      const int x = it.lo[0] + q.x, y = it.lo[1] + q.y, z = it.lo[2] + q.z;
+      const bool ins = x >= it.slo[0] && x < it.shi[0] && y >= it.slo[1] && y < it.shi[1] &&
+                       z >= it.slo[2] && z < it.shi[2];
+      const bool inp = x >= it.plo[0] && x < it.phi[0] && y >= it.plo[1] && y < it.phi[1] &&
+                       z >= it.plo[2] && z < it.phi[2];
+      if (!ins && !inp) continue;
+      const T v = refine_tap<T, N>(T2 + q.y * fs[0] + q.x, fs[0] * fs[1], z, clo[2]);
+      if (ins) {
+        const int par[3] = {x & 1, y & 1, z & 1};
+        bool take;
+        if (it.sel & 8) {
+          take = (par[0] | par[1] | par[2]) != 0;
+        } else {
+          take = true;
+          bool tang_odd = false;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          if (it.sel & (1 << a)) take = take && (par[a] == 0);
-          else tang_odd = tang_odd || (par[a] == 1);
+          for (int a = 0; a < 3; ++a) {
+            if (it.sel & (1 << a)) take = take && (par[a] == 0);
+            else tang_odd = tang_odd || (par[a] == 1);
+          }
+          take = take && tang_odd;
         }
-        take = take && tang_odd;
+        if (take) g.field[m * nb3 + (z * NB + y) * NB + x] = v;
       }
-      if (take) g.field[m * nb3 + ((int64_t)z * nb + y) * nb + x] = v;
-    } else {
-      T* out = it.buf ? g.scratch : g.patch;
-      out[it.off + ((int64_t)(z - it.rlo[2]) * it.rsz[1] + (y - it.rlo[1])) * it.rsz[0] +
-          (x - it.rlo[0])] = v;
+      if (inp)
+        g.patch[it.off + ((int64_t)(z - it.rlo[2]) * it.rsz[1] + (y - it.rlo[1])) * it.rsz[0] +
+                (x - it.rlo[0])] = v;
     }
-  }
-}
-
-// ------------------------------------------------------ restriction (f->c)
-template <typename T, int N, int NT>
-__device__ __forceinline__ T fine_view(const DevGrid<T>& g, const RItem& it, int L, int ox, int oy,
-                                       int oz, int px, int py, int pz) {
-  // level-(L+1) point p relative to 2*origin(C)
-  const int id = owner_id(g, it.blk, 1, px, py, pz);
-  T v = T(0);
-  if (id < 0) return v;
-  if (g.lev[id] == L + 1) {
-    leaf_value(g, id, L + 1, 2 * ox + px, 2 * oy + py, 2 * oz + pz, v);
-    return v;
-  }
-  if (g.lev[id] > L + 1) {  // finer still: injection (never produced by the owner map)
-    leaf_value(g, id, L + 1, 2 * ox + px, 2 * oy + py, 2 * oz + pz, v);
-    return v;
-  }
-  const int gx = px - it.glo[0], gy = py - it.glo[1], gz = pz - it.glo[2];
-  if ((unsigned)gx >= (unsigned)it.gsz[0] || (unsigned)gy >= (unsigned)it.gsz[1] ||
-      (unsigned)gz >= (unsigned)it.gsz[2]) {
-    atomicAdd(g.err, 1);
-    return v;
-  }
-  return g.scratch[it.goff + ((int64_t)gz * it.gsz[1] + gy) * it.gsz[0] + gx];
-}
-
-template <typename T, int N, int NT>
-__global__ __launch_bounds__(256) void k_rview(DevGrid<T> g, const RItem* __restrict__ items) {
-  extern __shared__ unsigned char lds_raw[];
-  T* lds = reinterpret_cast<T*>(lds_raw);
-  const RItem it = items[blockIdx.x];
-  const int m = it.blk;
-  const int L = g.lev[m];
-  const int nb = g.nb;
-  const int ox = g.ijk[3 * m] * nb, oy = g.ijk[3 * m + 1] * nb, oz = g.ijk[3 * m + 2] * nb;
-  constexpr int H = Ha<N, NT>::R;
-  int qs[3], flo[3], fsz[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    qs[a] = it.hi[a] - it.lo[a];
-    flo[a] = 2 * it.lo[a] - H;
-    fsz[a] = 2 * (qs[a] - 1) + 1 + 2 * H;
-  }
-  T* R1 = lds;                              // [fz][fy][qx]
-  T* R2 = R1 + qs[0] * fsz[1] * fsz[2];     // [fz][qy][qx]
-  const int n1 = qs[0] * fsz[1] * fsz[2];
-  for (int i = threadIdx.x; i < n1; i += blockDim.x) {
-    const int qx = i % qs[0];
-    const int fy = (i / qs[0]) % fsz[1];
-    const int fz = i / (qs[0] * fsz[1]);
-    const int px = 2 * (it.lo[0] + qx), py = flo[1] + fy, pz = flo[2] + fz;
-    T acc = T(0);
-#pragma unroll
-    for (int o = -H; o <= H; ++o) {
-      if (Ha<N, NT>::c(o) != 0.0)
-        acc += T(Ha<N, NT>::c(o)) * fine_view<T, N, NT>(g, it, L, ox, oy, oz, px + o, py, pz);
-    }
-    R1[i] = acc;
-  }
-  __syncthreads();
-  const int n2 = qs[0] * qs[1] * fsz[2];
-  for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-    const int qx = i % qs[0];
-    const int qy = (i / qs[0]) % qs[1];
-    const int fz = i / (qs[0] * qs[1]);
-    const int c = 2 * qy + H;  // window index of fine 2*(lo+qy)
-    T acc = T(0);
-#pragma unroll
-    for (int o = -H; o <= H; ++o) {
-      if (Ha<N, NT>::c(o) != 0.0)
-        acc += T(Ha<N, NT>::c(o)) * R1[(fz * fsz[1] + c + o) * qs[0] + qx];
-    }
-    R2[i] = acc;
-  }
-  __syncthreads();
-  const int n3 = qs[0] * qs[1] * qs[2];
-  for (int i = threadIdx.x; i < n3; i += blockDim.x) {
-    const int qx = i % qs[0];
-    const int qy = (i / qs[0]) % qs[1];
-    const int qz = i / (qs[0] * qs[1]);
-    const int c = 2 * qz + H;
-    T acc = T(0);
-#pragma unroll
-    for (int o = -H; o <= H; ++o) {
-      if (Ha<N, NT>::c(o) != 0.0)
-        acc += T(Ha<N, NT>::c(o)) * R2[((c + o) * qs[1] + qy) * qs[0] + qx];
-    }
-    const int x = it.lo[0] + qx, y = it.lo[1] + qy, z = it.lo[2] + qz;
-    g.patch[it.off + ((int64_t)(z - it.rlo[2]) * it.rsz[1] + (y - it.rlo[1])) * it.rsz[0] +
-            (x - it.rlo[0])] = acc;
   }
 }
 
@@ -419,6 +460,123 @@ __device__ __forceinline__ void make_desc(const DevGrid<T>& g, int b, int r, Des
   d.sz = sx * sy;
   d.off = po - lx - (int64_t)ly * sx - (int64_t)lz * sx * sy;
   d.patch = 1;
+}
+
+// ------------------------------------------------------ restriction (f->c)
+// One workgroup per RItem.  Pass 1 reduces along the item's thinnest axis n:
+// each thread reads whole columns of the fine block's ghost-filled field into
+// registers and applies H^a at the coarse points of the column.  Passes 2 and
+// 3 apply H^a along the two other axes in LDS.
+template <typename T, int N, int NT, int NB, int MAXQ>
+__global__ __launch_bounds__(256) void k_restrict(DevGrid<T> g, const RItem* __restrict__ items) {
+  extern __shared__ unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  __shared__ Desc desc[27];
+  __shared__ CellTab ct;
+  constexpr int H = Ha<N, NT>::R;
+  constexpr int XS = 2 * (MAXQ - 1) + 1 + 2 * H;
+  const RItem it = items[xcd_item(blockIdx.x, gridDim.x)];
+  const int F = it.fblk;
+  const int tid = threadIdx.x;
+  const int L = g.lev[F];
+  if (tid < 27) {
+    make_desc(g, F, tid, desc[tid]);
+    if (tid != 13) {
+      const int rx = tid % 3, ry = (tid / 3) % 3, rz = tid / 9;
+      const int cx = rx == 0 ? 0 : (rx == 1 ? 1 : 3);
+      const int cy = ry == 0 ? 0 : (ry == 1 ? 1 : 3);
+      const int cz = rz == 0 ? 0 : (rz == 1 ? 1 : 3);
+      if (g.lev[g.cmap[F * 64 + (cz * 4 + cy) * 4 + cx]] > L) desc[tid].patch = 2;  // injection
+    }
+  }
+  load_cells(g, F, ct);
+  int qlo[3], qs[3], xlo[3], xs[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    qlo[a] = it.lo[a] - it.sh[a];
+    qs[a] = it.hi[a] - it.lo[a];
+    xlo[a] = 2 * qlo[a] - H;
+    xs[a] = 2 * (qs[a] - 1) + 1 + 2 * H;
+  }
+  // reduction order: n (thinnest), then a1, then a2
+  int n = 0;
+  if (qs[1] < qs[n]) n = 1;
+  if (qs[2] < qs[n]) n = 2;
+  const int a1 = n == 0 ? 1 : 0, a2 = n == 2 ? 1 : 2;
+  T* R1 = lds;                               // [xs_a2][xs_a1][qs_n]
+  T* R2 = R1 + qs[n] * xs[a1] * xs[a2];      // [xs_a2][qs_a1][qs_n]
+  const int ox = g.ijk[3 * F] * NB, oy = g.ijk[3 * F + 1] * NB, oz = g.ijk[3 * F + 2] * NB;
+  const int nt = blockDim.x;
+  __syncthreads();
+  {
+    const int ncol = xs[a1] * xs[a2];
+    // unit step along n and column origin, as scalars (no runtime-indexed
+    // arrays, which would live in scratch memory)
+    const int ex = n == 0, ey = n == 1, ez = n == 2;
+    for (int cidx = tid; cidx < ncol; cidx += nt) {
+      const int c1 = cidx % xs[a1], c2 = cidx / xs[a1];
+      const int b1 = xlo[a1] + c1, b2 = xlo[a2] + c2;
+      const int px0 = n == 0 ? xlo[0] : (a1 == 0 ? b1 : b2);
+      const int py0 = n == 1 ? xlo[1] : (a1 == 1 ? b1 : b2);
+      const int pz0 = n == 2 ? xlo[2] : (a1 == 2 ? b1 : b2);
+      T col[XS];
+#pragma unroll
+      for (int j = 0; j < XS; ++j) {
+        col[j] = T(0);
+        if (j < xs[n]) {
+          const int px = px0 + ex * j, py = py0 + ey * j, pz = pz0 + ez * j;
+          const int rx = px < 0 ? 0 : (px < NB ? 1 : 2);
+          const int ry = py < 0 ? 0 : (py < NB ? 1 : 2);
+          const int rz = pz < 0 ? 0 : (pz < NB ? 1 : 2);
+          const Desc d = desc[rx + 3 * ry + 9 * rz];
+          if (d.patch == 2) col[j] = cell_value<T, NB>(g, ct, L, ox, oy, oz, px, py, pz);
+          else col[j] = (d.patch ? g.patch : g.field)[d.off + px + (int64_t)py * d.sy +
+                                                       (int64_t)pz * d.sz];
+        }
+      }
+      T* dst = R1 + cidx * qs[n];
+#pragma unroll
+      for (int k = 0; k < MAXQ; ++k) {
+        if (k < qs[n]) {
+          T acc = T(0);
+#pragma unroll
+          for (int o = -H; o <= H; ++o)
+            if (Ha<N, NT>::c(o) != 0.0) acc += T(Ha<N, NT>::c(o)) * col[2 * k + H + o];
+          dst[k] = acc;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const int cnt = qs[n] * qs[a1] * xs[a2];
+    Iter3 q(tid, nt, qs[n], qs[a1]);
+    for (int i = tid; i < cnt; i += nt, q.advance()) {
+      const T* src = R1 + (q.z * xs[a1] + 2 * q.y + H) * qs[n] + q.x;
+      T acc = T(0);
+#pragma unroll
+      for (int o = -H; o <= H; ++o)
+        if (Ha<N, NT>::c(o) != 0.0) acc += T(Ha<N, NT>::c(o)) * src[o * qs[n]];
+      R2[i] = acc;
+    }
+  }
+  __syncthreads();
+  {
+    const int cnt = qs[n] * qs[a1] * qs[a2];
+    Iter3 q(tid, nt, qs[n], qs[a1]);
+    for (int i = tid; i < cnt; i += nt, q.advance()) {
+      const T* src = R2 + ((2 * q.z + H) * qs[a1] + q.y) * qs[n] + q.x;
+      T acc = T(0);
+#pragma unroll
+      for (int o = -H; o <= H; ++o)
+        if (Ha<N, NT>::c(o) != 0.0) acc += T(Ha<N, NT>::c(o)) * src[o * qs[a1] * qs[n]];
+      const int c0 = n == 0 ? q.x : (a1 == 0 ? q.y : q.z);
+      const int cy1 = n == 1 ? q.x : (a1 == 1 ? q.y : q.z);
+      const int cz2 = n == 2 ? q.x : (a1 == 2 ? q.y : q.z);
+      g.patch[it.off + ((int64_t)(it.lo[2] + cz2 - it.rlo[2]) * it.rsz[1] + (it.lo[1] + cy1 - it.rlo[1])) * it.rsz[0] +
+              (it.lo[0] + c0 - it.rlo[0])] = acc;
+    }
+  }
 }
 
 template <int FD> struct FDW;
@@ -515,26 +673,48 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
       }
     }
   }
+  // Loads run two planes ahead of the stencil: col holds planes z-G..z+G,
+  // pf1 plane z+G+1 and the halo values of plane z+1 (hv1); at plane z the
+  // loads of plane z+G+2 and of the halo of z+2 are issued.
   T col[2 * G + 1];
 #pragma unroll
   for (int i = 0; i < 2 * G + 1; ++i) col[i] = load(tx, ty, i - G);
-  T hval[HPT];
+  T pf1 = load(tx, ty, G + 1);
+  // threads without a halo point load their own interior point instead, so
+  // that every thread issues the same number of loads per plane (partial
+  // vmcnt waits instead of full drains)
 #pragma unroll
-  for (int k = 0; k < HPT; ++k) hval[k] = hh[k] ? load(hx[k], hy[k], 0) : T(0);
+  for (int k = 0; k < HPT; ++k)
+    if (!hh[k]) {
+      hx[k] = tx;
+      hy[k] = ty;
+    }
+  T hval[HPT], hv1[HPT];
+#pragma unroll
+  for (int k = 0; k < HPT; ++k) {
+    hval[k] = load(hx[k], hy[k], 0);
+    hv1[k] = load(hx[k], hy[k], 1);
+  }
   const int64_t nb3 = (int64_t)NB * NB * NB;
   const int64_t obase = (int64_t)b * nb3 + (int64_t)ty * NB + tx;
   const T ux_y = vx_z[ty];  // rotating: u_x = -(y - cy) (per y); shear: per z
+  // u^n is also read one plane ahead, before that plane's stencil loads, so
+  // waiting for it never drains the loads issued later
+  T ucur = un[obase];
+  // fully unrolled: the register rotations below become renames, so the
+  // loads issued for later planes stay in flight across iterations
+#pragma unroll
   for (int z = 0; z < NB; ++z) {
     plane[(ty + G) * P + tx + G] = col[G];
 #pragma unroll
     for (int k = 0; k < HPT; ++k)
       if (hh[k]) plane[(hy[k] + G) * P + hx[k] + G] = hval[k];
-    T nxt = T(0), hnext[HPT];
-    if (z + G + 1 < NB + G) nxt = load(tx, ty, z + G + 1);
+    const T u0 = ucur;
+    if (z + 1 < NB) ucur = un[obase + (int64_t)(z + 1) * NB * NB];  // stage 1 passes its input
+    T pf2 = T(0), hv2[HPT];
+    if (z + G + 2 < NB + G) pf2 = load(tx, ty, z + G + 2);
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) hnext[k] = (hh[k] && z + 1 < NB) ? load(hx[k], hy[k], z + 1) : T(0);
-    T u0 = T(0);
-    if (a_un != T(0)) u0 = un[obase + (int64_t)z * NB * NB];
+    for (int k = 0; k < HPT; ++k) hv2[k] = (z + 2 < NB) ? load(hx[k], hy[k], z + 2) : T(0);
     __syncthreads();
     T dx = T(0), dy = T(0), dz = T(0);
 #pragma unroll
@@ -564,9 +744,13 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 2 * G; ++i) col[i] = col[i + 1];
-    col[2 * G] = nxt;
+    col[2 * G] = pf1;
+    pf1 = pf2;
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) hval[k] = hnext[k];
+    for (int k = 0; k < HPT; ++k) {
+      hval[k] = hv1[k];
+      hv1[k] = hv2[k];
+    }
   }
 }
 
@@ -574,19 +758,19 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
 // Forward transform (x, then y, then z) of the ghost-filled block in FP64,
 // per-block maxima of |gamma| over 27 (x-class, y-class, z-class) boxes:
 // class 0 = [0, nb), 1 = [0, eb), 2 = [nb-ef, nb).
-template <int N, int NT>
-__device__ __forceinline__ double ana(const double* line, int stride, int p) {
+template <int N, int NT, typename E>
+__device__ __forceinline__ double ana(const E* line, int stride, int p) {
   // analysis at position p of a line whose element 0 is position (p - 0)...
   // line points at position p; taps at line[o*stride]
   double acc = 0.0;
   if ((p & 1) == 0) {
 #pragma unroll
     for (int o = -Ha<N, NT>::R; o <= Ha<N, NT>::R; ++o)
-      if (Ha<N, NT>::c(o) != 0.0) acc += Ha<N, NT>::c(o) * line[o * stride];
+      if (Ha<N, NT>::c(o) != 0.0) acc += Ha<N, NT>::c(o) * double(line[o * stride]);
   } else {
 #pragma unroll
     for (int o = -Ga<N>::R; o <= Ga<N>::R; ++o)
-      if (Ga<N>::c(o) != 0.0) acc += Ga<N>::c(o) * line[o * stride];
+      if (Ga<N>::c(o) != 0.0) acc += Ga<N>::c(o) * double(line[o * stride]);
   }
   return acc;
 }
@@ -602,7 +786,7 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
   constexpr int HB = (HR - 1) > GR ? (HR - 1) : GR;    // back ghost depth
   constexpr int R = HR > GR ? HR : GR;                 // z ring half-width
   constexpr int P = NB + HF + HB;
-  __shared__ double pl[P * P];
+  __shared__ T pl[P * P];
   __shared__ double t1[P * NB];
   __shared__ Desc desc[27];
   __shared__ unsigned long long bmax[27];
@@ -623,29 +807,51 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
   double mz[3] = {0.0, 0.0, 0.0};
   const T* fbuf = g.field;
   const T* pbuf = g.patch;
-  auto load = [&](int x, int y, int z) -> double {
+  auto load = [&](int x, int y, int z) -> T {
     const int rx = x < 0 ? 0 : (x < NB ? 1 : 2);
     const int ry = y < 0 ? 0 : (y < NB ? 1 : 2);
     const int rz = z < 0 ? 0 : (z < NB ? 1 : 2);
     const Desc d = desc[rx + 3 * ry + 9 * rz];
     const T* buf = d.patch ? pbuf : fbuf;
-    return double(buf[d.off + x + (int64_t)y * d.sy + (int64_t)z * d.sz]);
+    return buf[d.off + x + (int64_t)y * d.sy + (int64_t)z * d.sz];
   };
-  // input planes z = -HF .. NB+HB-1; output plane zo = zi - R once available
-  for (int zi = -R; zi < NB + R; ++zi) {
-    const bool have = (zi >= -HF) && (zi < NB + HB);
+  // input planes z = -HF .. NB+HB-1; output plane zo = zi - R once available.
+  // The next plane's values are loaded into registers while the current
+  // plane is transformed (software pipelining of the global loads).
+  constexpr int LPT = (P * P + NB * NB - 1) / (NB * NB);
+  // Two planes in flight with ping-pong register buffers: the buffer of plane
+  // zi is refilled with plane zi + 2 right after it is stored to LDS, so no
+  // register holding an outstanding load is ever copied (a copy would force
+  // a wait for the load).  The ring starts as zeros, which stand for the
+  // planes below -HF that no filter tap reaches.
+  // Every fetch issues exactly LPT loads (clamped indices, values past the
+  // plane or the last plane are never stored) so that the compiler can wait
+  // for a given plane with a partial vmcnt instead of draining all loads.
+  auto fetch = [&](T* dst, int z) {
+    const int zz = z < NB + HB - 1 ? z : NB + HB - 1;
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) {
+      int i = tid + k * NB * NB;
+      i = i < P * P ? i : P * P - 1;
+      dst[k] = load(i % P - HF, i / P - HF, zz);
+    }
+  };
+  auto body = [&](int zi, T* cur) {
+    const bool have = zi < NB + HB;
     if (have) {
-      for (int i = tid; i < P * P; i += NB * NB) {
-        const int x = i % P - HF, y = i / P - HF;
-        pl[i] = load(x, y, zi);
+#pragma unroll
+      for (int k = 0; k < LPT; ++k) {
+        const int i = tid + k * NB * NB;
+        if (i < P * P) pl[i] = cur[k];
       }
     }
     __syncthreads();
     if (have) {
+      fetch(cur, zi + 2);
       for (int i = tid; i < P * NB; i += NB * NB) {
         const int x = i % NB;       // output x
         const int yy = i / NB;      // input y row (window index)
-        t1[i] = ana<N, NT>(pl + yy * P + x + HF, 1, x);
+        t1[i] = ana<N, NT>(pl + yy * P + x + HF, 1, x);  // FP64 from field precision
       }
     }
     __syncthreads();
@@ -675,6 +881,14 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
       if (slot >= 0)
         det_out[(int64_t)slot * NB * NB * NB + ((int64_t)zo * NB + ty) * NB + tx] = isdet ? gsum : 0.0;
     }
+  };
+  T nx0[LPT], nx1[LPT];
+  fetch(nx0, -HF);
+  fetch(nx1, -HF + 1);
+  // the ring window is aligned so that output plane zo = zi - R
+  for (int zi = -HF; zi < NB + R; zi += 2) {
+    body(zi, nx0);
+    if (zi + 1 < NB + R) body(zi + 1, nx1);
   }
   // fold into the 27 boxes that contain this column
   const bool inx[3] = {true, tx < eb, tx >= NB - ef};
@@ -937,10 +1151,16 @@ __global__ void k_fill(T* dst, size_t n) {
     else { constexpr int N_ = 6, NT_ = 2; CALL; }                    \
   } while (0)
 
+template <typename T, int NB>
+static void gview_nb(const DevGrid<T>& g, Wavelet w, const GItem* items, int n, int lds, hipStream_t s) {
+  MR_WAVELET_SWITCH(w, MR_LAUNCH((k_gview<T, N_, NT_, NB>), dim3(n), dim3(256), lds, s, g, items));
+}
 template <typename T>
 static void gview_t(const void* dg, Wavelet w, const GItem* items, int n, int lds, hipStream_t s) {
   const DevGrid<T>& g = *static_cast<const DevGrid<T>*>(dg);
-  MR_WAVELET_SWITCH(w, hipLaunchKernelGGL((k_gview<T, N_, NT_>), dim3(n), dim3(256), lds, s, g, items));
+  if (g.nb == 8) gview_nb<T, 8>(g, w, items, n, lds, s);
+  else if (g.nb == 16) gview_nb<T, 16>(g, w, items, n, lds, s);
+  else gview_nb<T, 24>(g, w, items, n, lds, s);
 }
 void launch_gview(bool f32, const void* dg, Wavelet w, const GItem* items, int n, int lds,
                   hipStream_t s) {
@@ -949,10 +1169,16 @@ void launch_gview(bool f32, const void* dg, Wavelet w, const GItem* items, int n
   else gview_t<double>(dg, w, items, n, lds, s);
 }
 
+template <typename T, int NB>
+static void rview_nb(const DevGrid<T>& g, Wavelet w, const RItem* items, int n, int lds, hipStream_t s) {
+  MR_WAVELET_SWITCH(w, MR_LAUNCH((k_restrict<T, N_, NT_, NB, 6>), dim3(n), dim3(256), lds, s, g, items));
+}
 template <typename T>
 static void rview_t(const void* dg, Wavelet w, const RItem* items, int n, int lds, hipStream_t s) {
   const DevGrid<T>& g = *static_cast<const DevGrid<T>*>(dg);
-  MR_WAVELET_SWITCH(w, hipLaunchKernelGGL((k_rview<T, N_, NT_>), dim3(n), dim3(256), lds, s, g, items));
+  if (g.nb == 8) rview_nb<T, 8>(g, w, items, n, lds, s);
+  else if (g.nb == 16) rview_nb<T, 16>(g, w, items, n, lds, s);
+  else rview_nb<T, 24>(g, w, items, n, lds, s);
 }
 void launch_rview(bool f32, const void* dg, Wavelet w, const RItem* items, int n, int lds,
                   hipStream_t s) {
@@ -965,9 +1191,8 @@ template <typename T, int FD, int NB>
 static void rhs_nb(const DevGrid<T>& g, const void* un, void* out, double a, double b, double dt,
                    const VelDev& v, int first, int n, hipStream_t s) {
   const int nxcd = (n >= 64) ? 8 : 1;
-  hipLaunchKernelGGL((k_rhs<T, FD, NB>), dim3(n), dim3(NB * NB), 0, s, g,
-                     static_cast<const T*>(un), static_cast<T*>(out), T(a), T(b), T(dt), v, first,
-                     nxcd);
+  MR_LAUNCH((k_rhs<T, FD, NB>), dim3(n), dim3(NB * NB), 0, s, g, static_cast<const T*>(un),
+            static_cast<T*>(out), T(a), T(b), T(dt), v, first, nxcd);
 }
 template <typename T>
 static void rhs_t(const void* dgv, const void* un, void* out, int fd, double a, double b, double dt,
@@ -994,8 +1219,8 @@ void launch_rhs(bool f32, const void* dg, const void* un, void* out, int fd, int
 template <typename T, int NB>
 static void details_nb(const DevGrid<T>& g, Wavelet w, int ef, int eb, double* bands,
                        const int32_t* slot, double* det, int first, int n, hipStream_t s) {
-  MR_WAVELET_SWITCH(w, hipLaunchKernelGGL((k_details<T, NB, N_, NT_>), dim3(n), dim3(NB * NB), 0,
-                                          s, g, ef, eb, bands, slot, det, first));
+  MR_WAVELET_SWITCH(w, MR_LAUNCH((k_details<T, NB, N_, NT_>), dim3(n), dim3(NB * NB), 0, s, g, ef,
+                                 eb, bands, slot, det, first));
 }
 void launch_details(bool f32, const void* dgv, Wavelet w, int ef, int eb, double* bands,
                     const int32_t* slot, double* det, int first, int n, hipStream_t s) {

@@ -248,17 +248,21 @@ static int gview_lds(const GItem& it, int N, size_t esz) {
     cs[a] = floordiv(it.hi[a] - 1, 2) + N / 2 + 1 - clo;
     fs[a] = it.hi[a] - it.lo[a];
   }
-  return int(esz * (size_t(cs[0]) * cs[1] * cs[2] + size_t(fs[0]) * cs[1] * cs[2] +
-                    size_t(fs[0]) * fs[1] * cs[2]));
+  return int(esz * (size_t(fs[0]) * cs[1] * cs[2] +
+                    std::max(size_t(cs[0]) * cs[1] * cs[2], size_t(fs[0]) * fs[1] * cs[2])));
 }
 
 static int rview_lds(const RItem& it, int H, size_t esz) {
-  int qs[3], fsz[3];
+  int qs[3], xs[3];
   for (int a = 0; a < 3; ++a) {
     qs[a] = it.hi[a] - it.lo[a];
-    fsz[a] = 2 * (qs[a] - 1) + 1 + 2 * H;
+    xs[a] = 2 * (qs[a] - 1) + 1 + 2 * H;
   }
-  return int(esz * (size_t(qs[0]) * fsz[1] * fsz[2] + size_t(qs[0]) * qs[1] * fsz[2]));
+  int n = 0;
+  if (qs[1] < qs[n]) n = 1;
+  if (qs[2] < qs[n]) n = 2;
+  const int a1 = n == 0 ? 1 : 0, a2 = n == 2 ? 1 : 2;
+  return int(esz * (size_t(qs[n]) * xs[a1] * xs[a2] + size_t(qs[n]) * qs[a1] * xs[a2]));
 }
 
 static const int kLdsBudget = 48 * 1024;
@@ -292,8 +296,11 @@ static void push_tiled(std::vector<Item>& out, Item it, F lds_of) {
 
 static int Hreach(int N, int Nt) { return Nt ? N : 0; }
 
-// Work lists of one ghost reconstruction at depth D: substitution slabs,
-// c->f patches, fine views and f->c restrictions.
+// Work lists of one ghost reconstruction at depth D: substitution slabs and
+// c->f patches (one launch), then f->c restrictions by the fine blocks (a
+// second launch, which reads the fine blocks' substituted values and their
+// c->f patches).  c->f patches are filled to max(D, reach of H^a) so that a
+// fine block's restriction window is covered by its own ghost layer.
 static mr_status build_lists(mr_grid* g, int D, Lists& L) {
   L.g.clear();
   L.r.clear();
@@ -301,11 +308,12 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
   L.out_points = 0;
   const int nb = g->nb, N = g->N, Nt = g->Nt, Dw = g->Dw;
   const int H = Hreach(N, Nt);
+  const int Dc = std::min(Dw, std::max(D, H));
   const size_t esz = g->esz;
   auto glds = [&](const GItem& it) { return gview_lds(it, N, esz); };
   auto rlds = [&](const RItem& it) { return rview_lds(it, H, esz); };
-  std::vector<RItem> rtmp;
   const int n = int(g->leaves.size());
+  const int hb = nb / 2;
   for (int b = 0; b < n; ++b) {
     const int Lb = g->leaves[b].L;
     for (int r = 0; r < 27; ++r) {
@@ -315,126 +323,79 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
       const int rr[3] = {r % 3, (r / 3) % 3, r / 9};
       int rlo[3], rhi[3], blo[3], bhi[3];
       region_box(nb, Dw, r, rlo, rhi);
-      region_box(nb, D, r, blo, bhi);
       if (lr < Lb) {
-        // substitution slab (READING R-SUB)
-        GItem s{};
-        s.blk = b;
-        s.up = 0;
-        s.mode = 0;
-        s.sel = Nt ? 8 : 0;
-        bool empty = false;
+        // one item per fine/coarse interface: substitution slab (READING
+        // R-SUB) and c->f patch share the staged coarse samples
+        GItem it{};
+        it.blk = b;
+        it.sel = Nt ? 8 : 0;
+        bool sempty = false;
         for (int a = 0; a < 3; ++a) {
           const int d = rr[a] - 1;
-          if (d == 0) { s.lo[a] = 0; s.hi[a] = nb; }
+          if (d == 0) { it.slo[a] = 0; it.shi[a] = nb; }
           else {
-            s.sel |= (1 << a);
+            it.sel |= (1 << a);
             if (Nt) {
-              if (d < 0) { s.lo[a] = 0; s.hi[a] = N; }
-              else { s.lo[a] = nb - N + 1; s.hi[a] = nb; }
+              if (d < 0) { it.slo[a] = 0; it.shi[a] = N; }
+              else { it.slo[a] = nb - N + 1; it.shi[a] = nb; }
             } else {
-              if (d < 0) { s.lo[a] = 0; s.hi[a] = N - 1; }
-              else { s.lo[a] = nb - N + 2; s.hi[a] = nb - 1; }
+              if (d < 0) { it.slo[a] = 0; it.shi[a] = N - 1; }
+              else { it.slo[a] = nb - N + 2; it.shi[a] = nb - 1; }
             }
           }
-          if (s.hi[a] <= s.lo[a]) empty = true;
+          if (it.shi[a] <= it.slo[a]) sempty = true;
         }
-        if (!Nt && (s.sel & 7) == 7) empty = true;  // corner: no tangential axis
-        if (!empty) push_tiled(L.g, s, glds);
-        // c->f patch
-        GItem c{};
-        c.blk = b;
-        c.up = 0;
-        c.mode = 1;
-        c.buf = 0;
-        c.off = g->poff[size_t(b) * 27 + r];
-        for (int a = 0; a < 3; ++a) {
-          c.lo[a] = blo[a];
-          c.hi[a] = bhi[a];
-          c.rlo[a] = rlo[a];
-          c.rsz[a] = rhi[a] - rlo[a];
-        }
-        L.out_points += box_size(blo, bhi);
-        push_tiled(L.g, c, glds);
-      } else {
-        RItem it{};
-        it.blk = b;
+        if (!Nt && (it.sel & 7) == 7) sempty = true;  // corner: no tangential axis
+        region_box(nb, Dc, r, blo, bhi);
         it.off = g->poff[size_t(b) * 27 + r];
         for (int a = 0; a < 3; ++a) {
-          it.lo[a] = blo[a];
-          it.hi[a] = bhi[a];
+          if (sempty) { it.slo[a] = 0; it.shi[a] = 0; }
+          it.plo[a] = blo[a];
+          it.phi[a] = bhi[a];
           it.rlo[a] = rlo[a];
           it.rsz[a] = rhi[a] - rlo[a];
+          it.lo[a] = sempty ? blo[a] : std::min(blo[a], it.slo[a]);
+          it.hi[a] = sempty ? bhi[a] : std::max(bhi[a], it.shi[a]);
         }
         L.out_points += box_size(blo, bhi);
-        rtmp.clear();
-        push_tiled(rtmp, it, rlds);
-        for (RItem& t : rtmp) {
-          // fine view: level-(L+1) points of the restriction window held by
-          // coarser leaves (their G_{L+1} comes from a refinement into scratch)
-          t.gsz[0] = t.gsz[1] = t.gsz[2] = 0;
-          if (Nt) {
-            int flo[3], fhi[3];
-            for (int a = 0; a < 3; ++a) {
-              flo[a] = 2 * t.lo[a] - H;
-              fhi[a] = 2 * (t.hi[a] - 1) + H + 1;
-            }
-            int glo[3] = {1 << 30, 1 << 30, 1 << 30}, ghi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
-            bool any = false;
-            // cells of nb level-(L+1) points: index c = floor((p + nb) / nb)
-            int c0[3], c1[3];
-            for (int a = 0; a < 3; ++a) {
-              c0[a] = floordiv(flo[a] + nb, nb);
-              c1[a] = floordiv(fhi[a] - 1 + nb, nb);
-              if (c0[a] < 0 || c1[a] > 3) return fail(MR_EINVAL, "restriction window leaves the owner map");
-            }
-            for (int cz = c0[2]; cz <= c1[2]; ++cz)
-              for (int cy = c0[1]; cy <= c1[1]; ++cy)
-                for (int cx = c0[0]; cx <= c1[0]; ++cx) {
-                  const int id = g->cmap[size_t(b) * 64 + (cz * 4 + cy) * 4 + cx];
-                  if (g->leaves[id].L > Lb) continue;
-                  const int cc[3] = {cx, cy, cz};
-                  for (int a = 0; a < 3; ++a) {
-                    const int lo = std::max(flo[a], (cc[a] - 1) * nb);
-                    const int hi = std::min(fhi[a], cc[a] * nb);
-                    glo[a] = std::min(glo[a], lo);
-                    ghi[a] = std::max(ghi[a], hi);
-                  }
-                  any = true;
-                }
-            if (any) {
-              GItem fv{};
-              fv.blk = b;
-              fv.up = 1;
-              fv.mode = 1;
-              fv.buf = 1;
-              fv.off = L.scratch_elems;
-              for (int a = 0; a < 3; ++a) {
-                fv.lo[a] = glo[a];
-                fv.hi[a] = ghi[a];
-                fv.rlo[a] = glo[a];
-                fv.rsz[a] = ghi[a] - glo[a];
-                t.glo[a] = glo[a];
-                t.gsz[a] = ghi[a] - glo[a];
-                // the refinement samples (level L) must stay inside the map
-                const int cl = floordiv(glo[a], 2) - N / 2;
-                const int ch = floordiv(ghi[a] - 1, 2) + N / 2;
-                if (cl < -nb / 2 || ch >= 3 * nb / 2)
-                  return fail(MR_EINVAL, "fine view samples leave the owner map");
-              }
-              t.goff = L.scratch_elems;
-              L.scratch_elems += box_size(glo, ghi);
-              push_tiled(L.g, fv, glds);
-            }
-          }
-          L.r.push_back(t);
+        push_tiled(L.g, it, glds);
+      } else {
+        // f->c: each finer leaf covering this region restricts its part
+        region_box(nb, D, r, blo, bhi);
+        int c0[3], c1[3];
+        for (int a = 0; a < 3; ++a) {
+          c0[a] = rr[a] == 0 ? 0 : (rr[a] == 1 ? 1 : 3);
+          c1[a] = rr[a] == 0 ? 0 : (rr[a] == 1 ? 2 : 3);
         }
+        for (int cz = c0[2]; cz <= c1[2]; ++cz)
+          for (int cy = c0[1]; cy <= c1[1]; ++cy)
+            for (int cx = c0[0]; cx <= c1[0]; ++cx) {
+              const int cc[3] = {cx, cy, cz};
+              RItem it{};
+              it.fblk = g->cmap[size_t(b) * 64 + (cz * 4 + cy) * 4 + cx];
+              it.cblk = b;
+              it.off = g->poff[size_t(b) * 27 + r];
+              bool empty = false;
+              for (int a = 0; a < 3; ++a) {
+                const int lo = (cc[a] - 1) * hb, hi = cc[a] * hb;
+                it.lo[a] = std::max(blo[a], lo);
+                it.hi[a] = std::min(bhi[a], hi);
+                it.sh[a] = lo;
+                it.rlo[a] = rlo[a];
+                it.rsz[a] = rhi[a] - rlo[a];
+                if (it.hi[a] <= it.lo[a]) empty = true;
+              }
+              if (empty) continue;
+              if (g->leaves[it.fblk].L != Lb + 1)
+                return fail(MR_EINVAL, "finer region not covered by level+1 leaves");
+              L.out_points += box_size(it.lo, it.hi);
+              push_tiled(L.r, it, rlds);
+            }
       }
     }
   }
   // sample boxes of c->f and substitution items must stay inside the map
   for (const GItem& it : L.g) {
-    if (it.up) continue;
     for (int a = 0; a < 3; ++a) {
       const int cl = 2 * (floordiv(it.lo[a], 2) - N / 2);
       const int ch = 2 * (floordiv(it.hi[a] - 1, 2) + N / 2);
@@ -537,17 +498,22 @@ static AnyView anyview(mr_grid* g, void* field) {
   return v;
 }
 
-static void prof_begin(mr_grid* g, int fam, hipEvent_t* a) {
+// Kernel timers: events stamped by the runtime at the start and end of the
+// timed launch (hipExtLaunchKernel), or around a sequence of launches in the
+// plain (one launch per block) mode.
+static void prof_begin(mr_grid* g, int fam, hipEvent_t* a, hipEvent_t* b, bool tight) {
+  (void)fam;
+  *a = *b = nullptr;
   if (!g->prof.on) return;
   (void)hipEventCreate(a);
-  (void)hipEventRecord(*a, g->stream);
-  (void)fam;
+  (void)hipEventCreate(b);
+  if (tight) set_launch_events(*a, *b);
+  else (void)hipEventRecord(*a, g->stream);
 }
-static void prof_end(mr_grid* g, int fam, hipEvent_t a, int64_t points) {
+static void prof_end(mr_grid* g, int fam, hipEvent_t a, hipEvent_t b, bool tight, int64_t points) {
   if (!g->prof.on) return;
-  hipEvent_t b;
-  (void)hipEventCreate(&b);
-  (void)hipEventRecord(b, g->stream);
+  if (tight) set_launch_events(nullptr, nullptr);
+  else (void)hipEventRecord(b, g->stream);
   g->prof.recs.push_back({a, b, fam});
   g->prof.points[fam] = points;
 }
@@ -557,47 +523,53 @@ static void ghost_fill(mr_grid* g, void* field, Lists& L) {
   AnyView v = anyview(g, field);
   const Wavelet w{g->N, g->Nt};
   const bool plain = g->cfg.exec_mode == 1;
-  hipEvent_t a = nullptr;
-  prof_begin(g, 2, &a);
-  if (plain) {
-    for (size_t i = 0; i < L.g.size(); ++i)
-      launch_gview(g->f32, v.raw, w, static_cast<const GItem*>(L.dg.p) + i, 1, L.lds_g, g->stream);
-  } else {
-    launch_gview(g->f32, v.raw, w, static_cast<const GItem*>(L.dg.p), int(L.g.size()), L.lds_g, g->stream);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (!L.g.empty()) {
+    prof_begin(g, 2, &a, &b, !plain);
+    if (plain) {
+      for (size_t i = 0; i < L.g.size(); ++i)
+        launch_gview(g->f32, v.raw, w, static_cast<const GItem*>(L.dg.p) + i, 1, L.lds_g, g->stream);
+    } else {
+      launch_gview(g->f32, v.raw, w, static_cast<const GItem*>(L.dg.p), int(L.g.size()), L.lds_g, g->stream);
+    }
+    prof_end(g, 2, a, b, !plain, L.out_points);
   }
-  prof_end(g, 2, a, L.out_points);
-  prof_begin(g, 3, &a);
-  if (plain) {
-    for (size_t i = 0; i < L.r.size(); ++i)
-      launch_rview(g->f32, v.raw, w, static_cast<const RItem*>(L.dr.p) + i, 1, L.lds_r, g->stream);
-  } else {
-    launch_rview(g->f32, v.raw, w, static_cast<const RItem*>(L.dr.p), int(L.r.size()), L.lds_r, g->stream);
+  if (!L.r.empty()) {
+    prof_begin(g, 3, &a, &b, !plain);
+    if (plain) {
+      for (size_t i = 0; i < L.r.size(); ++i)
+        launch_rview(g->f32, v.raw, w, static_cast<const RItem*>(L.dr.p) + i, 1, L.lds_r, g->stream);
+    } else {
+      launch_rview(g->f32, v.raw, w, static_cast<const RItem*>(L.dr.p), int(L.r.size()), L.lds_r, g->stream);
+    }
+    prof_end(g, 3, a, b, !plain, L.out_points);
   }
-  prof_end(g, 3, a, L.out_points);
 }
 
 static void rhs_stage(mr_grid* g, void* y, const void* un, void* out, double a_un, double b_y,
                       double dt, const VelDev& vel) {
   AnyView v = anyview(g, y);
   const int n = int(g->leaves.size());
-  hipEvent_t a = nullptr;
-  prof_begin(g, 0, &a);
-  if (g->cfg.exec_mode == 1) {
+  hipEvent_t a = nullptr, e = nullptr;
+  const bool plain = g->cfg.exec_mode == 1;
+  prof_begin(g, 0, &a, &e, !plain);
+  if (plain) {
     for (int b = 0; b < n; ++b)
       launch_rhs(g->f32, v.raw, un, out, g->cfg.fd_order, g->G, a_un, b_y, dt, vel, b, 1, g->stream);
   } else {
     launch_rhs(g->f32, v.raw, un, out, g->cfg.fd_order, g->G, a_un, b_y, dt, vel, 0, n, g->stream);
   }
-  prof_end(g, 0, a, int64_t(n) * g->nb * g->nb * g->nb);
+  prof_end(g, 0, a, e, !plain, int64_t(n) * g->nb * g->nb * g->nb);
 }
 
 static void details_pass(mr_grid* g, void* field, const int32_t* det_slot, double* det_out) {
   AnyView v = anyview(g, field);
   const int n = int(g->leaves.size());
   const Wavelet w{g->N, g->Nt};
-  hipEvent_t a = nullptr;
-  prof_begin(g, 1, &a);
-  if (g->cfg.exec_mode == 1) {
+  hipEvent_t a = nullptr, e = nullptr;
+  const bool plain = g->cfg.exec_mode == 1;
+  prof_begin(g, 1, &a, &e, !plain);
+  if (plain) {
     for (int b = 0; b < n; ++b)
       launch_details(g->f32, v.raw, w, g->Ef, g->Eb, static_cast<double*>(g->d_bands.p), det_slot,
                      det_out, b, 1, g->stream);
@@ -605,7 +577,7 @@ static void details_pass(mr_grid* g, void* field, const int32_t* det_slot, doubl
     launch_details(g->f32, v.raw, w, g->Ef, g->Eb, static_cast<double*>(g->d_bands.p), det_slot,
                    det_out, 0, n, g->stream);
   }
-  prof_end(g, 1, a, int64_t(n) * g->nb * g->nb * g->nb);
+  prof_end(g, 1, a, e, !plain, int64_t(n) * g->nb * g->nb * g->nb);
   launch_combine(v.raw, static_cast<double*>(g->d_bands.p), g->cfg.detail_ext,
                  static_cast<double*>(g->d_norms.p), n, g->stream);
 }
@@ -1222,12 +1194,14 @@ mr_status mr_ghost_get(mr_grid* g, int32_t field, int32_t depth, int64_t b0, int
 }
 
 mr_status mr_details(mr_grid* g, int32_t field, double* norms, int32_t on_device) {
-  if (!g || !norms || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
+  if (!g || (!norms && !on_device) || field < 0 || field >= g->cfg.n_fields)
+    return fail(MR_EINVAL, "bad argument");
   ghost_fill(g, g->fields[field].p, g->wide);
   details_pass(g, g->fields[field].p, nullptr, nullptr);
   const size_t n = g->leaves.size();
   if (on_device) {
-    HIPCHK(hipMemcpyAsync(norms, g->d_norms.p, n * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+    if (norms && n)
+      HIPCHK(hipMemcpyAsync(norms, g->d_norms.p, n * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
     return MR_OK;
   }
   HIPCHK(hipMemcpyAsync(norms, g->d_norms.p, n * sizeof(double), hipMemcpyDeviceToHost, g->stream));
@@ -1370,7 +1344,13 @@ mr_status mr_prof_read(mr_grid* g, const char* kernel, double* total_ms, int64_t
   return MR_OK;
 }
 
-mr_status mr_tree_stats(const mr_grid* g, int64_t out[5]) {
+mr_status mr_sync(mr_grid* g) {
+  if (!g) return fail(MR_EINVAL, "null grid");
+  HIPCHK(hipStreamSynchronize(g->stream));
+  return check_err(g);
+}
+
+mr_status mr_tree_stats(const mr_grid* g, int64_t out[10]) {
   if (!g || !out) return fail(MR_EINVAL, "null argument");
   int lo = 99, hi = -1;
   for (const Key& k : g->leaves) {
@@ -1380,10 +1360,15 @@ mr_status mr_tree_stats(const mr_grid* g, int64_t out[5]) {
   out[0] = int64_t(g->leaves.size());
   out[1] = g->stage.out_points;
   int64_t subs = 0;
-  for (const GItem& it : g->stage.g) subs += it.mode == 0;
+  for (const GItem& it : g->stage.g) subs += it.shi[0] > it.slo[0];
   out[2] = subs;
   out[3] = hi;
   out[4] = lo;
+  out[5] = int64_t(g->stage.g.size());
+  out[6] = int64_t(g->stage.r.size());
+  out[7] = g->stage.lds_g;
+  out[8] = g->stage.lds_r;
+  out[9] = g->patch_elems;
   return MR_OK;
 }
 

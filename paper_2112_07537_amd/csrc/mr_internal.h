@@ -10,40 +10,41 @@
 namespace mr {
 
 // Zero-detail refinement of a box (coarse-extension assumption, section
-// 2.2.2): the tensor Deslauriers-Dubuc refinement of the level-(Lb-1) samples
-// around a box of level-Lb points, Lb = level(blk) + up.  mode 0 writes the
-// substituted points of field[blk] (section 2.2.4); mode 1 writes the whole box
-// into a patch (c->f ghosts) or into scratch (fine view for a restriction).
+// 2.2.2): the tensor Deslauriers-Dubuc refinement of the level-(L-1) samples
+// around a box of level-L points of block blk.  One item serves one
+// fine/coarse interface of blk: points of the box inside the substitution
+// slab that pass the selector overwrite field[blk] (section 2.2.4); points
+// inside the patch box are the c->f ghost values written into blk's patch.
 struct GItem {
-  int32_t blk;      // block whose owner map resolves the samples
-  int32_t up;       // 0: box at blk's level; 1: box one level finer
-  int32_t mode;     // 0: substitution into field[blk]; 1: box into out buffer
-  int32_t sel;      // mode 0: bits 0..2 = axes facing the coarser leaf,
-                    //         bit 3 = lifted wavelet (every non-all-even point)
-  int32_t lo[3];    // box [lo, hi) in coordinates relative to blk's origin
-  int32_t hi[3];    //   scaled to the box level
-  int32_t rlo[3];   // mode 1: origin and extent of the output array
+  int32_t blk;      // fine block whose owner map resolves the samples
+  int32_t sel;      // bits 0..2 = axes facing the coarser leaf,
+                    // bit 3 = lifted wavelet (every non-all-even point)
+  int32_t lo[3];    // box [lo, hi) over which the refinement is evaluated,
+  int32_t hi[3];    //   relative to blk's origin at blk's level
+  int32_t slo[3];   // substitution slab (empty when slo >= shi on an axis)
+  int32_t shi[3];
+  int32_t plo[3];   // c->f patch box (empty when plo >= phi on an axis)
+  int32_t phi[3];
+  int32_t rlo[3];   // patch region origin / extent (output indexing)
   int32_t rsz[3];
-  int32_t buf;      // mode 1: 0 = patch buffer, 1 = scratch buffer
-  int32_t pad;
-  int64_t off;      // mode 1: element offset of the output array
+  int64_t off;      // patch offset
 };
 
 // Restriction of finer data to coarse ghost points (f->c, ghosting Part 2):
-// [H^a]^3 of the level-(L+1) view around each level-L point of a box of
-// block C's ghost region.  Samples held by coarser leaves come from a fine
-// view box computed by a GItem with up = 1 into scratch.
+// a fine block F coarsens its ghost-filled level-L field ([H^a]^3; injection
+// for N.0) at the level-(L-1) points that lie in the ghost region of its
+// coarser neighbour C, and writes them into C's patch.  Inside the
+// restriction window, points held by leaves finer than F are injected.
 struct RItem {
-  int32_t blk;      // coarse block C
-  int32_t lo[3];    // box of C-level points, relative to C's origin
+  int32_t fblk;     // fine block F
+  int32_t cblk;     // coarse block C
+  int32_t lo[3];    // output box, C-relative coordinates at C's level
   int32_t hi[3];
-  int32_t rlo[3];   // patch region origin / extent for output indexing
+  int32_t sh[3];    // F-relative coarse coordinate = C-relative - sh
+  int32_t rlo[3];   // C's patch region origin / extent
   int32_t rsz[3];
-  int32_t glo[3];   // fine view box (level L+1, relative to 2*origin(C))
-  int32_t gsz[3];   //   gsz = 0: no coarser-held samples
   int32_t pad;
-  int64_t off;      // patch offset
-  int64_t goff;     // scratch offset of the fine view
+  int64_t off;      // C's patch offset
 };
 
 // One separable pass of a box operation used by adaptation (refine, coarsen,
@@ -132,6 +133,7 @@ void launch_fill(bool f32, void* dst, size_t n, hipStream_t s);
 void launch_pass(bool f32, const void* dg, Wavelet w, int filter, int axis, int src_mode,
                  int dst_mode, const PItem* items, int n_items, const double* din, double* dout,
                  const double* det, const int32_t* det_slot, void* dst, hipStream_t s);
-const char* device_error(hipError_t e);
+// Events to be stamped at the start and end of the next launch (NULL: none).
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
 
 }  // namespace mr

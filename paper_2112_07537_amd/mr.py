@@ -72,6 +72,7 @@ def load():
         "mr_prof_read": [P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                          C.POINTER(C.c_int64)],
         "mr_tree_stats": [P, P],
+        "mr_sync": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -213,7 +214,7 @@ class Grid:
         _check(lib().mr_details(self._h, field, _ptr(a), 0))
         return a
 
-    def details_async(self, dev_ptr, field=0):
+    def details_async(self, dev_ptr=None, field=0):
         _check(lib().mr_details(self._h, field, C.c_void_p(dev_ptr), 1))
 
     def adapt(self, field=0, max_iter=64):
@@ -244,7 +245,10 @@ class Grid:
         _check(lib().mr_prof_read(self._h, kernel.encode(), C.byref(ms), C.byref(n), C.byref(pts)))
         return ms.value, n.value, pts.value
 
+    def sync(self):
+        _check(lib().mr_sync(self._h))
+
     def tree_stats(self):
-        a = np.zeros(5, np.int64)
+        a = np.zeros(10, np.int64)
         _check(lib().mr_tree_stats(self._h, _ptr(a)))
         return a
