@@ -25,8 +25,8 @@
  *  - Host pointers passed in are caller-owned and only read/written during
  *    the call.  Device memory is owned by the library (hipMalloc) and freed
  *    by mr_grid_destroy.
- *  - Streams: device work is issued on the hipStream_t given at creation
- *    (NULL = default stream).  mr_ghost, mr_rk3_step and mr_details with
+ *  - Streams: device work is issued on the hipStream_t given at creation;
+ *    with NULL the library creates a private non-blocking stream.  mr_ghost, mr_rk3_step and mr_details with
  *    on_device = 1 are asynchronous; every other call synchronises the stream.
  *  - A grid handle is not thread-safe.
  */
@@ -108,7 +108,8 @@ typedef struct {
   int64_t n_blocks;   /* leaves after adaptation                          */
 } mr_adapt_stats;
 
-/* Create a grid.  hip_stream: a hipStream_t or NULL.  The tree starts as the
+/* Create a grid.  hip_stream: a hipStream_t, or NULL for a private stream
+ * owned by the grid.  The tree starts as the
  * uniform tree at level_min with zero fields.  Warns (mr_last_error) but
  * succeeds when eps_refine/eps_coarsen <= 2^N (section 2.2.5: flip-flops). */
 mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, mr_grid** out);

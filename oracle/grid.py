@@ -394,37 +394,46 @@ class Grid:
         odd = (idx[:, None, None] + idx[None, :, None] + idx[None, None, :]) > 0
         return np.where(odd, T, 0.0)
 
-    def norms(self):
-        """Block criterion of section 2.2.5: max |gamma^{L-1}| per block, with
-        the extension band (READING R-EXT) taken from same-level neighbours."""
-        det = {k: self.block_details(k) for k in self.blocks}
-        own = {k: float(np.max(np.abs(v))) for k, v in det.items()}
+    def block_norm(self, key, det=None):
+        """Block criterion of section 2.2.5 for one block: max |gamma^{L-1}|
+        over its own detail positions and, with the extension (READING R-EXT),
+        over the band of E_f / E_b points of each same-level neighbour next to
+        it (Table 3, 3D coarse region extension).  ``det`` caches
+        block_details results."""
+        det = {} if det is None else det
+
+        def D(k):
+            if k not in det:
+                det[k] = self.block_details(k)
+            return det[k]
+        best = float(np.max(np.abs(D(key))))
         if not self.detail_ext:
-            return own
+            return best
         Ef, Eb = DETAIL_EXT[(self.N, self.Nt)]
         nb = self.nb
-        out = {}
-        for key in self.blocks:
-            L, i, j, k = key
-            best = own[key]
-            n = 1 << L
-            for d in DIRS:
-                nk = (L, (i + d[0]) % n, (j + d[1]) % n, (k + d[2]) % n)
-                if nk not in self.blocks:
-                    continue
-                sl = []
-                for a in (2, 1, 0):          # z, y, x array axes
-                    if d[a] == 0:
-                        sl.append(slice(0, nb))
-                    elif d[a] == 1:
-                        sl.append(slice(0, Eb))
-                    else:
-                        sl.append(slice(nb - Ef, nb))
-                band = det[nk][tuple(sl)]
-                if band.size:
-                    best = max(best, float(np.max(np.abs(band))))
-            out[key] = best
-        return out
+        L, i, j, k = key
+        n = 1 << L
+        for d in DIRS:
+            nk = (L, (i + d[0]) % n, (j + d[1]) % n, (k + d[2]) % n)
+            if nk not in self.blocks:
+                continue
+            sl = []
+            for a in (2, 1, 0):          # z, y, x array axes
+                if d[a] == 0:
+                    sl.append(slice(0, nb))
+                elif d[a] == 1:
+                    sl.append(slice(0, Eb))
+                else:
+                    sl.append(slice(nb - Ef, nb))
+            band = D(nk)[tuple(sl)]
+            if band.size:
+                best = max(best, float(np.max(np.abs(band))))
+        return best
+
+    def norms(self):
+        """Block criterion of section 2.2.5 for every block (see block_norm)."""
+        det = {}
+        return {k: self.block_norm(k, det) for k in self.blocks}
 
     # ------------------------------------------------------------- moments
     def moments(self):

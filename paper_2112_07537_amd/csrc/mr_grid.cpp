@@ -105,6 +105,7 @@ using namespace mr;
 struct mr_grid {
   mr_config cfg{};
   hipStream_t stream = nullptr;
+  bool own_stream = false;
   bool f32 = false;
   int nb = 16, N = 4, Nt = 0, G = 2, Dw = 4;
   int Ef = 0, Eb = 0;
@@ -1007,6 +1008,15 @@ mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, mr_grid** out) 
   mr_grid* g = new mr_grid();
   g->cfg = c;
   g->stream = static_cast<hipStream_t>(hip_stream);
+  if (!g->stream) {
+    // a private non-blocking stream (default priority): the legacy NULL
+    // stream cannot be captured into a graph
+    if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete g;
+      return fail(MR_EHIP, "hipStreamCreateWithFlags failed");
+    }
+    g->own_stream = true;
+  }
   g->f32 = c.prec == MR_F32;
   g->esz = g->f32 ? 4 : 8;
   g->nb = c.nb;
@@ -1084,6 +1094,7 @@ mr_status mr_grid_destroy(mr_grid* g) {
                     &g->d_scratch, &g->d_err, &g->d_bands, &g->d_norms, &g->d_icpar, &g->d_mom,
                     &g->stage.dg, &g->stage.dr, &g->wide.dg, &g->wide.dr};
   for (DevBuf* b : bufs) b->release();
+  if (g->own_stream) (void)hipStreamDestroy(g->stream);
   delete g;
   return MR_OK;
 }

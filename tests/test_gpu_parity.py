@@ -240,3 +240,32 @@ def test_abi_errors_on_gpu():
     too_deep += [(3, c & 1, (c >> 1) & 1, (c >> 2) & 1) for c in range(8)]
     with pytest.raises(mr.MRError):
         g.set_tree(too_deep)                 # level 3 next to level 1
+
+
+@pytest.mark.parametrize("prec", ["f64"])
+def test_adaptive_run_parity(prec):
+    """Initial grid (refine-only loop, then one adaptation) and three steps of
+    RK3 + adaptation, GPU against the oracle: identical trees, fields within
+    1e-12 of max|phi|."""
+    nb, N, Nt, fd = 16, 4, 2, 4
+    ic = ("gauss", wl.gauss_params([(0.43, 0.52, 0.47)], [0.08], [1.0]))
+    kw = dict(level_min=1, level_max=3, eps_refine=3e-3, eps_coarsen=2e-5)
+    g = mr.Grid(nb, N, Nt, fd_order=fd, prec=prec, max_blocks=4096, **kw)
+    g.init_ic(*ic)
+    o = og.Grid(nb, N, Nt, fd_order=fd, **kw)
+    o.init_ic(wl.ic_function(ic))
+    vel = ("const", (1.0, 0.5, 0.25))
+    v = mr.velocity(vel[0], *vel[1])
+    for step in range(4):
+        meta = [tuple(int(x) for x in m) for m in g.block_meta()]
+        assert sorted(meta) == o.keys(), step
+        got = g.field_get()
+        err = max(np.abs(got[b] - o.blocks[k]).max() for b, k in enumerate(meta))
+        assert err <= 1e-12, (step, err)
+        if step == 3:
+            break
+        dt = g.cfl_dt(v, 0.5)
+        g.rk3_step(dt, v)
+        g.adapt()
+        o.rk3_step(dt, vel)
+        o.adapt()
