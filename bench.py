@@ -24,6 +24,8 @@ from paper_2112_07537_amd import mr  # noqa: E402
 from paper_2112_07537_amd import workloads as wl  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+DEVICE_SRC = os.path.join(ROOT, "paper_2112_07537_amd", "csrc", "mr_device.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "c5_hbm_traffic.md")
 METRIC = "RK3-step grid points/s (ghost+details+RHS) & % HBM peak, FP32-batched vs FP64-plain"
 
 
@@ -76,37 +78,77 @@ def timed_steps(g, cfg, steps, warmup, adapt_every=0):
     return t, points, t_adapt, n_adapt
 
 
-def cpu_baseline(g, cfg, n_sample=12, seed=1234):
+def cpu_baseline(g, cfg, n_sample=400, seed=1234, budget_s=15.0):
     """The FP64 oracle timed on a seeded sample of the same grid: per sampled
     block, three stages of (substitution + ghost reconstruction + RHS) and one
-    detail transform, computed from the GPU's current state."""
+    detail transform, computed from the GPU's current state.  Blocks are taken
+    in the seeded order until about `budget_s` seconds of CPU work."""
     from oracle import grid as og
     meta = [tuple(int(v) for v in m) for m in g.block_meta()]
     data = g.field_get()
     o = og.Grid(cfg["nb"], cfg["N"], cfg["Nt"], fd_order=cfg["fd"], level_min=cfg["level_min"],
                 level_max=cfg["level_max"], eps_refine=cfg["eps_refine"],
                 eps_coarsen=cfg["eps_coarsen"])
-    o.blocks = {k: data[b] for b, k in enumerate(meta)}  # upcast lazily below
+    data = data.astype(np.float64)
+    o.blocks = {k: data[b] for b, k in enumerate(meta)}
     o._index()
     rng = np.random.default_rng(seed)
     sample = [meta[i] for i in rng.choice(len(meta), size=min(n_sample, len(meta)), replace=False)]
-    for k in set(sample):
-        o.blocks[k] = o.blocks[k].astype(np.float64)
     kind, p = wl.velocity_spec(cfg["vel"])
     vel = (kind, p)
+    from threadpoolctl import threadpool_limits
+    limiter = threadpool_limits(limits=1)   # the oracle on exactly one core
     t0 = time.perf_counter()
+    done = 0
     for k in sample:
         for _ in range(3):
             for key, z, y, x, v in o.substitution_writes(k):
                 o.blocks[key][z, y, x] = v
             o.rhs_block(k, vel)
         o.block_details(k)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
     t = time.perf_counter() - t0
-    pts = len(sample) * cfg["nb"] ** 3
+    limiter.unregister()
+    sample = sample[:done]
+    pts = done * cfg["nb"] ** 3
     return {"value": pts / t, "unit": "points/s", "cores": 1, "kind": "oracle",
             "sample": "%d seeded blocks of the %s grid (%d^3 points each): 3 x (substitution + "
                       "ghost + RHS) + 1 detail transform per block, FP64 numpy, %.1f s" %
                       (len(sample), cfg["name"], cfg["nb"], t)}
+
+
+def counter_traffic(workload):
+    """HBM bytes per k_rhs launch from the committed hardware-counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None when
+    the summary is for another workload or the kernels changed since."""
+    import hashlib
+    if not workload.startswith("c5_") or not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "device_source_sha256"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(DEVICE_SRC, "rb").read()).hexdigest()
+    if kv.get("device_source_sha256") != sha or "c5_adaptive_l3-9_nb24_w62_fd6_f32_eps3e-06" != workload:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def calibrate_copy(mib=2048, reps=3):
+    """A plain device copy of known size (torch's elementwise copy kernel),
+    run under the same hardware counters as the path so that the counters'
+    bytes can be scaled to true HBM bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "reps": reps}))
 
 
 def main():
@@ -119,7 +161,12 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--eps-refine", type=float, default=None)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 2 GiB device copy (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the whole octree on a single "
               "MI355X and has no multi-GPU path (requested --gpus %d)" % args.gpus,
@@ -174,6 +221,15 @@ def main():
         log("cpu: %.4g points/s" % cpu["value"])
     g.close()
 
+    # -- FP64 batched path (same kernels in FP64)
+    if not args.no_plain:
+        log("fp64 batched path")
+        gb = make_grid(cfg, prec="f64", exec_mode=0)
+        tb, pb, _, _ = timed_steps(gb, cfg, max(2, args.steps // 4), 1)
+        extra["fp64_batched_points_per_s"] = pb / tb
+        log("fp64 batched: %.4g points/s" % extra["fp64_batched_points_per_s"])
+        gb.close()
+
     # -- FP64 plain path (one launch per block per operation, no graph)
     if not args.no_plain:
         log("fp64 plain path")
@@ -195,7 +251,7 @@ def main():
                    "wavelet": "%d.%d" % (cfg["N"], cfg["Nt"]), "fd_order": cfg["fd"],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(cfg["name"]),
                      "kernel": "k_rhs (FD advection + SSP-RK3 stage)",
                      "bytes_per_launch": rhs_bytes / max(1, rhs_n),
                      "avg_launch_ms": rhs_ms / max(1, rhs_n)},

@@ -279,6 +279,34 @@ __device__ __forceinline__ T cell_value(const DevGrid<T>& g, const CellTab& ct, 
   return g.field[(int64_t)ct.id[c] * (NB * NB * NB) + (lz * NB + ly) * NB + lx];
 }
 
+// Branch-free form of cell_value: the element index of the value (clamped into
+// the owning leaf) and a flag set when the point is outside the map or not on
+// the leaf's grid.  Lets a thread issue several loads before waiting on any.
+template <int NB>
+__device__ __forceinline__ int64_t cell_index(const CellTab& ct, int L, int Ox, int Oy, int Oz,
+                                              int px, int py, int pz, int& bad) {
+  constexpr int H = NB / 2;
+  unsigned ux = unsigned(px + H), uy = unsigned(py + H), uz = unsigned(pz + H);
+  bad |= int(ux >= 4u * H) | int(uy >= 4u * H) | int(uz >= 4u * H);
+  ux = min(ux, 4u * H - 1u);
+  uy = min(uy, 4u * H - 1u);
+  uz = min(uz, 4u * H - 1u);
+  const int c = ((uz / H) * 4 + uy / H) * 4 + ux / H;
+  const int W = NB << L;
+  int X = wrap1(Ox + px, W), Y = wrap1(Oy + py, W), Z = wrap1(Oz + pz, W);
+  const int l = ct.lev[c];
+  bad |= int(l < L) & ((X | Y | Z) & 1);
+  X = l > L ? (X << 1) : (l < L ? (X >> 1) : X);
+  Y = l > L ? (Y << 1) : (l < L ? (Y >> 1) : Y);
+  Z = l > L ? (Z << 1) : (l < L ? (Z >> 1) : Z);
+  unsigned lx = unsigned(X - ct.ox[c]), ly = unsigned(Y - ct.oy[c]), lz = unsigned(Z - ct.oz[c]);
+  bad |= int(lx >= unsigned(NB)) | int(ly >= unsigned(NB)) | int(lz >= unsigned(NB));
+  lx = min(lx, unsigned(NB - 1));
+  ly = min(ly, unsigned(NB - 1));
+  lz = min(lz, unsigned(NB - 1));
+  return (int64_t)ct.id[c] * (NB * NB * NB) + int((lz * NB + ly) * NB + lx);
+}
+
 // Row iteration helper: rows of a 2D index space (a, b) in [0,na) x [0,nb_),
 // visited with stride `step` starting at `start`, without divisions.
 struct RowIt {
@@ -357,13 +385,30 @@ __global__ __launch_bounds__(256) void k_gview(DevGrid<T> g, const GItem* __rest
   const int ox = g.ijk[3 * m] * NB, oy = g.ijk[3 * m + 1] * NB, oz = g.ijk[3 * m + 2] * NB;
   const int nt = blockDim.x;
   __syncthreads();
-  // coarse samples: level-(L-1) points c, i.e. level-L points p = 2c
+  // coarse samples: level-(L-1) points c, i.e. level-L points p = 2c; U
+  // loads in flight per thread before the first LDS store
   {
+    constexpr int U = 8;
     const int n = cs[0] * cs[1] * cs[2];
     Iter3 q(threadIdx.x, nt, cs[0], cs[1]);
-    for (int i = threadIdx.x; i < n; i += nt, q.advance())
-      S[i] = cell_value<T, NB>(g, ct, L, ox, oy, oz, 2 * (clo[0] + q.x), 2 * (clo[1] + q.y),
-                               2 * (clo[2] + q.z));
+    int bad = 0;
+    for (int i0 = threadIdx.x; i0 < n; i0 += U * nt) {
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        int b = 0;
+        const int64_t e = cell_index<NB>(ct, L, ox, oy, oz, 2 * (clo[0] + q.x),
+                                         2 * (clo[1] + q.y), 2 * (clo[2] + q.z), b);
+        const bool in = i0 + u * nt < n;
+        bad |= b & int(in);
+        v[u] = g.field[in ? e : 0];
+        q.advance();
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * nt < n) S[i0 + u * nt] = v[u];
+    }
+    if (bad) atomicAdd(g.err, 1);
   }
   __syncthreads();
   {
@@ -519,21 +564,24 @@ __global__ __launch_bounds__(256) void k_restrict(DevGrid<T> g, const RItem* __r
       const int px0 = n == 0 ? xlo[0] : (a1 == 0 ? b1 : b2);
       const int py0 = n == 1 ? xlo[1] : (a1 == 1 ? b1 : b2);
       const int pz0 = n == 2 ? xlo[2] : (a1 == 2 ? b1 : b2);
+      // every load of the column is issued before the first use: positions
+      // past the column end are clamped onto its last point (never used), and
+      // the rare injection points only change the address
       T col[XS];
+      int bad = 0;
 #pragma unroll
       for (int j = 0; j < XS; ++j) {
-        col[j] = T(0);
-        if (j < xs[n]) {
-          const int px = px0 + ex * j, py = py0 + ey * j, pz = pz0 + ez * j;
-          const int rx = px < 0 ? 0 : (px < NB ? 1 : 2);
-          const int ry = py < 0 ? 0 : (py < NB ? 1 : 2);
-          const int rz = pz < 0 ? 0 : (pz < NB ? 1 : 2);
-          const Desc d = desc[rx + 3 * ry + 9 * rz];
-          if (d.patch == 2) col[j] = cell_value<T, NB>(g, ct, L, ox, oy, oz, px, py, pz);
-          else col[j] = (d.patch ? g.patch : g.field)[d.off + px + (int64_t)py * d.sy +
-                                                       (int64_t)pz * d.sz];
-        }
+        const int jj = j < xs[n] ? j : xs[n] - 1;
+        const int px = px0 + ex * jj, py = py0 + ey * jj, pz = pz0 + ez * jj;
+        const int rx = px < 0 ? 0 : (px < NB ? 1 : 2);
+        const int ry = py < 0 ? 0 : (py < NB ? 1 : 2);
+        const int rz = pz < 0 ? 0 : (pz < NB ? 1 : 2);
+        const Desc d = desc[rx + 3 * ry + 9 * rz];
+        int64_t e = d.off + px + (int64_t)py * d.sy + (int64_t)pz * d.sz;
+        if (d.patch == 2) e = cell_index<NB>(ct, L, ox, oy, oz, px, py, pz, bad);
+        col[j] = (d.patch == 1 ? g.patch : g.field)[e];
       }
+      if (bad) atomicAdd(g.err, 1);
       T* dst = R1 + cidx * qs[n];
 #pragma unroll
       for (int k = 0; k < MAXQ; ++k) {
