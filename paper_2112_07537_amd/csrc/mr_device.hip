@@ -362,101 +362,170 @@ __device__ __forceinline__ int xcd_item(int i, int n) {
   return x * q + (x < r ? x : r) + k;
 }
 
+// Affine address table of the 64 owner-map cells of block m for coarse
+// samples: the level-(L-1) sample c (relative to m's origin, i.e. the
+// level-L point p = 2c) held by the leaf of cell k sits at element
+//   base[k] + step[k] * (c_x + NB c_y + NB^2 c_z)
+// of the field (step 1, 2 or 4 for a leaf one level coarser, at the same
+// level, one level finer).  The periodic wrap is constant inside a cell,
+// so it is folded into base.  Sets *bad for a leaf outside L-1..L+1.
+template <typename T, int NB>
+__device__ __forceinline__ void sample_table(const DevGrid<T>& g, int m, int L, int64_t* base,
+                                             int32_t* step, int* bad) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    constexpr int H = NB / 2;
+    const int id = g.cmap[m * 64 + t];
+    const int l = g.lev[id];
+    const int W = NB << L;
+    const int cc[3] = {t & 3, (t >> 2) & 3, t >> 4};
+    int64_t b = (int64_t)id * (NB * NB * NB);
+    int64_t mul = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int O = g.ijk[3 * m + a] * NB;
+      const int X0 = O + (cc[a] - 1) * H;
+      const int shift = X0 - wrap1(X0, W);
+      const int o = g.ijk[3 * id + a] * NB;
+      const int base_a = l == L ? (O - shift) - o : (l > L ? 2 * (O - shift) - o : (O - shift) / 2 - o);
+      b += mul * base_a;
+      mul *= NB;
+    }
+    base[t] = b;
+    step[t] = l == L ? 2 : (l > L ? 4 : 1);
+    if (l < L - 1 || l > L + 1) atomicAdd(bad, 1);
+  }
+}
+
+// One workgroup per GItem.  S = coarse samples [cs2][cs1][cs0], T1 = refined
+// along x [cs2][cs1][fs0], T2 = refined along y [cs2][fs1][fs0] (aliases S),
+// then z is refined and written out.  Each refinement pass computes pairs of
+// fine points (2c, 2c+1) from the samples c-N/2+1 .. c+N/2.
 template <typename T, int N, int NT, int NB>
 __global__ __launch_bounds__(256) void k_gview(DevGrid<T> g, const GItem* __restrict__ items) {
   extern __shared__ unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
-  __shared__ CellTab ct;
+  __shared__ int64_t cbase[64];
+  __shared__ int32_t cstep[64];
+  __shared__ uint8_t acell[3][32];
+  constexpr int J0 = 1 - N / 2;   // first DD tap offset
+  constexpr int HN = N / 2 - 1;   // index of sample c inside the window
   const GItem it = items[xcd_item(blockIdx.x, gridDim.x)];
   const int m = it.blk;
-  load_cells(g, m, ct);
   const int L = g.lev[m];
-  int clo[3], cs[3], fs[3];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  int clo[3], cs[3], fs[3], np[3], e[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    clo[a] = (it.lo[a] >> 1) - N / 2;
-    cs[a] = ((it.hi[a] - 1) >> 1) + N / 2 + 1 - clo[a];
+    const int p0 = it.lo[a] >> 1, p1 = (it.hi[a] - 1) >> 1;  // first / last pair
+    clo[a] = p0 + J0;
+    cs[a] = p1 - p0 + N;
     fs[a] = it.hi[a] - it.lo[a];
+    np[a] = p1 - p0 + 1;
+    e[a] = it.lo[a] & 1;   // 1: the first pair's even point is outside the box
   }
-  // S is dead once T1 is built, so T2 reuses its space
-  T* T1 = lds;                                                        // [cs2][cs1][fs0]
-  T* S = T1 + fs[0] * cs[1] * cs[2];                                  // [cs2][cs1][cs0]
-  T* T2 = S;                                                          // [cs2][fs1][fs0]
-  const int ox = g.ijk[3 * m] * NB, oy = g.ijk[3 * m + 1] * NB, oz = g.ijk[3 * m + 2] * NB;
-  const int nt = blockDim.x;
+  sample_table<T, NB>(g, m, L, cbase, cstep, g.err);
+  if (tid < 96) {
+    const int a = tid >> 5, i = tid & 31;
+    if (i < cs[a]) acell[a][i] = uint8_t((2 * (clo[a] + i) + NB / 2) / (NB / 2));
+  }
+  T* T1 = lds;
+  T* S = T1 + fs[0] * cs[1] * cs[2];
+  T* T2 = S;
   __syncthreads();
-  // coarse samples: level-(L-1) points c, i.e. level-L points p = 2c; U
-  // loads in flight per thread before the first LDS store
   {
-    constexpr int U = 8;
+    constexpr int U = 4;
     const int n = cs[0] * cs[1] * cs[2];
-    Iter3 q(threadIdx.x, nt, cs[0], cs[1]);
-    int bad = 0;
-    for (int i0 = threadIdx.x; i0 < n; i0 += U * nt) {
+    Iter3 q(tid, nt, cs[0], cs[1]);
+    for (int i0 = tid; i0 < n; i0 += U * nt) {
       T v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        int b = 0;
-        const int64_t e = cell_index<NB>(ct, L, ox, oy, oz, 2 * (clo[0] + q.x),
-                                         2 * (clo[1] + q.y), 2 * (clo[2] + q.z), b);
         const bool in = i0 + u * nt < n;
-        bad |= b & int(in);
-        v[u] = g.field[in ? e : 0];
+        const int qx = in ? q.x : 0, qy = in ? q.y : 0, qz = in ? q.z : 0;
+        const int k = (acell[2][qz] * 4 + acell[1][qy]) * 4 + acell[0][qx];
+        const int64_t idx = cbase[k] + (int64_t)cstep[k] * ((clo[0] + qx) + NB * (clo[1] + qy) +
+                                                            NB * NB * (clo[2] + qz));
+        v[u] = g.field[idx];
         q.advance();
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (i0 + u * nt < n) S[i0 + u * nt] = v[u];
     }
-    if (bad) atomicAdd(g.err, 1);
   }
   __syncthreads();
-  {
-    const int n = fs[0] * cs[1] * cs[2];
-    Iter3 q(threadIdx.x, nt, fs[0], cs[1]);
-    for (int i = threadIdx.x; i < n; i += nt, q.advance())
-      T1[i] = refine_tap<T, N>(S + (q.z * cs[1] + q.y) * cs[0], 1, it.lo[0] + q.x, clo[0]);
+  {  // x: pairs j along x, rows (y, z) of samples
+    const int n = np[0] * cs[1] * cs[2];
+    Iter3 q(tid, nt, np[0], cs[1]);
+    for (int i = tid; i < n; i += nt, q.advance()) {
+      const int r = q.z * cs[1] + q.y;
+      const T* src = S + r * cs[0] + q.x;
+      T od = T(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) od += T(DD<N>::w(k)) * src[k];
+      const int x0 = 2 * q.x - e[0];
+      T* dst = T1 + r * fs[0];
+      if (x0 >= 0) dst[x0] = src[HN];
+      if (x0 + 1 < fs[0]) dst[x0 + 1] = od;
+    }
   }
   __syncthreads();
-  {
-    const int n = fs[0] * fs[1] * cs[2];
-    Iter3 q(threadIdx.x, nt, fs[0], fs[1]);
-    for (int i = threadIdx.x; i < n; i += nt, q.advance())
-      T2[i] = refine_tap<T, N>(T1 + q.z * fs[0] * cs[1] + q.x, fs[0], it.lo[1] + q.y, clo[1]);
+  {  // y: pairs along y, columns (x, z)
+    const int n = fs[0] * np[1] * cs[2];
+    Iter3 q(tid, nt, fs[0], np[1]);
+    for (int i = tid; i < n; i += nt, q.advance()) {
+      const T* src = T1 + (q.z * cs[1] + q.y) * fs[0] + q.x;
+      T od = T(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) od += T(DD<N>::w(k)) * src[k * fs[0]];
+      const int y0 = 2 * q.y - e[1];
+      T* dst = T2 + q.z * fs[1] * fs[0] + q.x;
+      if (y0 >= 0) dst[y0 * fs[0]] = src[HN * fs[0]];
+      if (y0 + 1 < fs[1]) dst[(y0 + 1) * fs[0]] = od;
+    }
   }
   __syncthreads();
   constexpr int64_t nb3 = (int64_t)NB * NB * NB;
-  {
-    const int n = fs[0] * fs[1] * fs[2];
-    Iter3 q(threadIdx.x, nt, fs[0], fs[1]);
-    for (int i = threadIdx.x; i < n; i += nt, q.advance()) {
-      const int x = it.lo[0] + q.x, y = it.lo[1] + q.y, z = it.lo[2] + q.z;
-      const bool ins = x >= it.slo[0] && x < it.shi[0] && y >= it.slo[1] && y < it.shi[1] &&
-                       z >= it.slo[2] && z < it.shi[2];
-      const bool inp = x >= it.plo[0] && x < it.phi[0] && y >= it.plo[1] && y < it.phi[1] &&
-                       z >= it.plo[2] && z < it.phi[2];
-      if (!ins && !inp) continue;
-      const T v = refine_tap<T, N>(T2 + q.y * fs[0] + q.x, fs[0] * fs[1], z, clo[2]);
-      if (ins) {
-        const int par[3] = {x & 1, y & 1, z & 1};
-        bool take;
-        if (it.sel & 8) {
-          take = (par[0] | par[1] | par[2]) != 0;
-        } else {
-          take = true;
-          bool tang_odd = false;
+  const bool slab = (it.sel & 16) != 0;
+  {  // z: pairs along z, written out
+    const int n = fs[0] * fs[1] * np[2];
+    const int plane = fs[0] * fs[1];
+    Iter3 q(tid, nt, fs[0], fs[1]);
+    for (int i = tid; i < n; i += nt, q.advance()) {
+      const T* src = T2 + (q.z * fs[1] + q.y) * fs[0] + q.x;
+      T od = T(0);
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            if (it.sel & (1 << a)) take = take && (par[a] == 0);
-            else tang_odd = tang_odd || (par[a] == 1);
+      for (int k = 0; k < N; ++k) od += T(DD<N>::w(k)) * src[k * plane];
+      const T ev = src[HN * plane];
+      const int x = it.lo[0] + q.x, y = it.lo[1] + q.y;
+      const int z0 = it.lo[2] + 2 * q.z - e[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int z = z0 + h;
+        if (z < it.lo[2] || z >= it.hi[2]) continue;
+        const T v = h ? od : ev;
+        if (slab) {
+          const int par[3] = {x & 1, y & 1, z & 1};
+          bool take;
+          if (it.sel & 8) {
+            take = (par[0] | par[1] | par[2]) != 0;
+          } else {
+            take = true;
+            bool tang_odd = false;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              if (it.sel & (1 << a)) take = take && (par[a] == 0);
+              else tang_odd = tang_odd || (par[a] == 1);
+            }
+            take = take && tang_odd;
           }
-          take = take && tang_odd;
+          if (take) g.field[m * nb3 + (z * NB + y) * NB + x] = v;
+        } else {
+          g.patch[it.off + ((int64_t)(z - it.rlo[2]) * it.rsz[1] + (y - it.rlo[1])) * it.rsz[0] +
+                  (x - it.rlo[0])] = v;
         }
-        if (take) g.field[m * nb3 + (z * NB + y) * NB + x] = v;
       }
-      if (inp)
-        g.patch[it.off + ((int64_t)(z - it.rlo[2]) * it.rsz[1] + (y - it.rlo[1])) * it.rsz[0] +
-                (x - it.rlo[0])] = v;
     }
   }
 }

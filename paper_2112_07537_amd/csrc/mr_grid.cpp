@@ -242,11 +242,19 @@ static int floordiv(int a, int b) {
   return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
 }
 
+// Sample range of a refinement box along one axis: pairs p0..p1 of fine
+// points (2c, 2c+1) need the samples p0 + 1 - N/2 .. p1 + N/2.
+static void gview_samples(int lo, int hi, int N, int* clo, int* cs) {
+  const int p0 = floordiv(lo, 2), p1 = floordiv(hi - 1, 2);
+  *clo = p0 + 1 - N / 2;
+  *cs = p1 - p0 + N;
+}
+
 static int gview_lds(const GItem& it, int N, size_t esz) {
   int cs[3], fs[3];
   for (int a = 0; a < 3; ++a) {
-    const int clo = floordiv(it.lo[a], 2) - N / 2;
-    cs[a] = floordiv(it.hi[a] - 1, 2) + N / 2 + 1 - clo;
+    int clo;
+    gview_samples(it.lo[a], it.hi[a], N, &clo, &cs[a]);
     fs[a] = it.hi[a] - it.lo[a];
   }
   return int(esz * (size_t(fs[0]) * cs[1] * cs[2] +
@@ -325,41 +333,51 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
       int rlo[3], rhi[3], blo[3], bhi[3];
       region_box(nb, Dw, r, rlo, rhi);
       if (lr < Lb) {
-        // one item per fine/coarse interface: substitution slab (READING
-        // R-SUB) and c->f patch share the staged coarse samples
-        GItem it{};
-        it.blk = b;
-        it.sel = Nt ? 8 : 0;
+        // c->f patch of this region, depth Dc
+        GItem pt{};
+        pt.blk = b;
+        pt.sel = Nt ? 8 : 0;
+        for (int a = 0; a < 3; ++a)
+          if (rr[a] != 1) pt.sel |= (1 << a);
+        region_box(nb, Dc, r, blo, bhi);
+        pt.off = g->poff[size_t(b) * 27 + r];
+        for (int a = 0; a < 3; ++a) {
+          pt.lo[a] = blo[a];
+          pt.hi[a] = bhi[a];
+          pt.rlo[a] = rlo[a];
+          pt.rsz[a] = rhi[a] - rlo[a];
+        }
+        L.out_points += box_size(blo, bhi);
+        push_tiled(L.g, pt, glds);
+        // substitution slab of this interface (READING R-SUB), unless a
+        // coarser region facing a proper subset of the same axes exists: its
+        // slab contains this one (and the substituted values do not depend
+        // on which item computes them)
+        GItem sb = pt;
+        sb.sel |= 16;
         bool sempty = false;
         for (int a = 0; a < 3; ++a) {
           const int d = rr[a] - 1;
-          if (d == 0) { it.slo[a] = 0; it.shi[a] = nb; }
-          else {
-            it.sel |= (1 << a);
-            if (Nt) {
-              if (d < 0) { it.slo[a] = 0; it.shi[a] = N; }
-              else { it.slo[a] = nb - N + 1; it.shi[a] = nb; }
-            } else {
-              if (d < 0) { it.slo[a] = 0; it.shi[a] = N - 1; }
-              else { it.slo[a] = nb - N + 2; it.shi[a] = nb - 1; }
-            }
+          if (d == 0) { sb.lo[a] = 0; sb.hi[a] = nb; }
+          else if (Nt) {
+            if (d < 0) { sb.lo[a] = 0; sb.hi[a] = N; }
+            else { sb.lo[a] = nb - N + 1; sb.hi[a] = nb; }
+          } else {
+            if (d < 0) { sb.lo[a] = 0; sb.hi[a] = N - 1; }
+            else { sb.lo[a] = nb - N + 2; sb.hi[a] = nb - 1; }
           }
-          if (it.shi[a] <= it.slo[a]) sempty = true;
+          if (sb.hi[a] <= sb.lo[a]) sempty = true;
         }
-        if (!Nt && (it.sel & 7) == 7) sempty = true;  // corner: no tangential axis
-        region_box(nb, Dc, r, blo, bhi);
-        it.off = g->poff[size_t(b) * 27 + r];
-        for (int a = 0; a < 3; ++a) {
-          if (sempty) { it.slo[a] = 0; it.shi[a] = 0; }
-          it.plo[a] = blo[a];
-          it.phi[a] = bhi[a];
-          it.rlo[a] = rlo[a];
-          it.rsz[a] = rhi[a] - rlo[a];
-          it.lo[a] = sempty ? blo[a] : std::min(blo[a], it.slo[a]);
-          it.hi[a] = sempty ? bhi[a] : std::max(bhi[a], it.shi[a]);
+        if (!Nt && (sb.sel & 7) == 7) sempty = true;  // corner: no tangential axis
+        const int facing = sb.sel & 7;
+        bool covered = false;
+        for (int sub = 1; sub < 8 && !covered; ++sub) {
+          if ((sub & facing) != sub || sub == facing) continue;
+          int r2 = 0, mul = 1;
+          for (int a = 0; a < 3; ++a, mul *= 3) r2 += mul * ((sub >> a) & 1 ? rr[a] : 1);
+          if (region_level(g, b, r2) < Lb) covered = true;
         }
-        L.out_points += box_size(blo, bhi);
-        push_tiled(L.g, it, glds);
+        if (!sempty && !covered) push_tiled(L.g, sb, glds);
       } else {
         // f->c: each finer leaf covering this region restricts its part
         region_box(nb, D, r, blo, bhi);
@@ -395,12 +413,15 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
       }
     }
   }
-  // sample boxes of c->f and substitution items must stay inside the map
+  // sample boxes of c->f and substitution items must stay inside the map,
+  // and their extent fits the kernel's per-axis cell table (32 samples)
   for (const GItem& it : L.g) {
     for (int a = 0; a < 3; ++a) {
-      const int cl = 2 * (floordiv(it.lo[a], 2) - N / 2);
-      const int ch = 2 * (floordiv(it.hi[a] - 1, 2) + N / 2);
-      if (cl < -nb / 2 || ch >= 3 * nb / 2) return fail(MR_EINVAL, "refinement samples leave the owner map");
+      int clo, cs;
+      gview_samples(it.lo[a], it.hi[a], N, &clo, &cs);
+      if (2 * clo < -nb / 2 || 2 * (clo + cs - 1) >= 3 * nb / 2)
+        return fail(MR_EINVAL, "refinement samples leave the owner map");
+      if (cs > 32) return fail(MR_EINVAL, "refinement item too wide");
     }
   }
   L.lds_g = 0;
@@ -1371,7 +1392,7 @@ mr_status mr_tree_stats(const mr_grid* g, int64_t out[10]) {
   out[0] = int64_t(g->leaves.size());
   out[1] = g->stage.out_points;
   int64_t subs = 0;
-  for (const GItem& it : g->stage.g) subs += it.shi[0] > it.slo[0];
+  for (const GItem& it : g->stage.g) subs += (it.sel & 16) != 0;
   out[2] = subs;
   out[3] = hi;
   out[4] = lo;

@@ -11,20 +11,17 @@ namespace mr {
 
 // Zero-detail refinement of a box (coarse-extension assumption, section
 // 2.2.2): the tensor Deslauriers-Dubuc refinement of the level-(L-1) samples
-// around a box of level-L points of block blk.  One item serves one
-// fine/coarse interface of blk: points of the box inside the substitution
-// slab that pass the selector overwrite field[blk] (section 2.2.4); points
-// inside the patch box are the c->f ghost values written into blk's patch.
+// around a box of level-L points of block blk.  A patch item writes the c->f
+// ghost values of one region of blk into blk's patch; a substitution item
+// overwrites the points of blk's slab next to a coarser leaf that pass the
+// selector (section 2.2.4).
 struct GItem {
   int32_t blk;      // fine block whose owner map resolves the samples
   int32_t sel;      // bits 0..2 = axes facing the coarser leaf,
-                    // bit 3 = lifted wavelet (every non-all-even point)
-  int32_t lo[3];    // box [lo, hi) over which the refinement is evaluated,
-  int32_t hi[3];    //   relative to blk's origin at blk's level
-  int32_t slo[3];   // substitution slab (empty when slo >= shi on an axis)
-  int32_t shi[3];
-  int32_t plo[3];   // c->f patch box (empty when plo >= phi on an axis)
-  int32_t phi[3];
+                    // bit 3 = lifted wavelet (every non-all-even point),
+                    // bit 4 = substitution item (else patch item)
+  int32_t lo[3];    // box [lo, hi) of level-L points, relative to blk's
+  int32_t hi[3];    //   origin at blk's level
   int32_t rlo[3];   // patch region origin / extent (output indexing)
   int32_t rsz[3];
   int64_t off;      // patch offset
