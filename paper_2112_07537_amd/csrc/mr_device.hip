@@ -633,24 +633,60 @@ __global__ __launch_bounds__(256) void k_restrict(DevGrid<T> g, const RItem* __r
       const int px0 = n == 0 ? xlo[0] : (a1 == 0 ? b1 : b2);
       const int py0 = n == 1 ? xlo[1] : (a1 == 1 ? b1 : b2);
       const int pz0 = n == 2 ? xlo[2] : (a1 == 2 ? b1 : b2);
-      // every load of the column is issued before the first use: positions
-      // past the column end are clamped onto its last point (never used), and
-      // the rare injection points only change the address
-      T col[XS];
-      int bad = 0;
+      // The column crosses at most three regions along n (before, inside,
+      // after the block); the two other coordinates are fixed, so each
+      // region is a pointer and a stride.  Every load of the column is
+      // issued before the first use; positions past the column end are
+      // clamped onto its last point (never used).
+      const int pn0 = n == 0 ? px0 : (n == 1 ? py0 : pz0);
+      const T* sp[3];
+      int32_t sst[3];
+      bool inj = false;
 #pragma unroll
-      for (int j = 0; j < XS; ++j) {
-        const int jj = j < xs[n] ? j : xs[n] - 1;
-        const int px = px0 + ex * jj, py = py0 + ey * jj, pz = pz0 + ez * jj;
-        const int rx = px < 0 ? 0 : (px < NB ? 1 : 2);
-        const int ry = py < 0 ? 0 : (py < NB ? 1 : 2);
-        const int rz = pz < 0 ? 0 : (pz < NB ? 1 : 2);
+      for (int rn = 0; rn < 3; ++rn) {
+        const int qx = n == 0 ? (rn == 0 ? -1 : (rn == 1 ? 0 : NB)) : px0;
+        const int qy = n == 1 ? (rn == 0 ? -1 : (rn == 1 ? 0 : NB)) : py0;
+        const int qz = n == 2 ? (rn == 0 ? -1 : (rn == 1 ? 0 : NB)) : pz0;
+        const int rx = qx < 0 ? 0 : (qx < NB ? 1 : 2);
+        const int ry = qy < 0 ? 0 : (qy < NB ? 1 : 2);
+        const int rz = qz < 0 ? 0 : (qz < NB ? 1 : 2);
         const Desc d = desc[rx + 3 * ry + 9 * rz];
-        int64_t e = d.off + px + (int64_t)py * d.sy + (int64_t)pz * d.sz;
-        if (d.patch == 2) e = cell_index<NB>(ct, L, ox, oy, oz, px, py, pz, bad);
-        col[j] = (d.patch == 1 ? g.patch : g.field)[e];
+        const int32_t st = n == 0 ? 1 : (n == 1 ? d.sy : d.sz);
+        // pointer of the column's position 0 (coordinate pn0) in this region
+        const int bx = n == 0 ? pn0 : px0, by = n == 1 ? pn0 : py0, bz = n == 2 ? pn0 : pz0;
+        sp[rn] = (d.patch == 1 ? g.patch : g.field) + d.off + bx + (int64_t)by * d.sy +
+                 (int64_t)bz * d.sz;
+        sst[rn] = st;
+        const bool used = rn == 0 ? pn0 < 0 : (rn == 1 ? (pn0 < NB && pn0 + xs[n] > 0)
+                                                        : pn0 + xs[n] > NB);
+        inj = inj || (used && d.patch == 2);
       }
-      if (bad) atomicAdd(g.err, 1);
+      const int j0 = -pn0, j1 = NB - pn0;   // region boundaries along the column
+      T col[XS];
+      if (!inj) {
+#pragma unroll
+        for (int j = 0; j < XS; ++j) {
+          const int jj = j < xs[n] ? j : xs[n] - 1;
+          const int rn = jj < j0 ? 0 : (jj < j1 ? 1 : 2);
+          col[j] = sp[rn][(int64_t)jj * sst[rn]];
+        }
+      } else {
+        // a finer-still leaf inside the window: resolve every point
+        int bad = 0;
+#pragma unroll
+        for (int j = 0; j < XS; ++j) {
+          const int jj = j < xs[n] ? j : xs[n] - 1;
+          const int px = px0 + ex * jj, py = py0 + ey * jj, pz = pz0 + ez * jj;
+          const int rx = px < 0 ? 0 : (px < NB ? 1 : 2);
+          const int ry = py < 0 ? 0 : (py < NB ? 1 : 2);
+          const int rz = pz < 0 ? 0 : (pz < NB ? 1 : 2);
+          const Desc d = desc[rx + 3 * ry + 9 * rz];
+          int64_t e = d.off + px + (int64_t)py * d.sy + (int64_t)pz * d.sz;
+          if (d.patch == 2) e = cell_index<NB>(ct, L, ox, oy, oz, px, py, pz, bad);
+          col[j] = (d.patch == 1 ? g.patch : g.field)[e];
+        }
+        if (bad) atomicAdd(g.err, 1);
+      }
       T* dst = R1 + cidx * qs[n];
 #pragma unroll
       for (int k = 0; k < MAXQ; ++k) {
@@ -892,7 +928,7 @@ __device__ __forceinline__ double ana(const E* line, int stride, int p) {
   return acc;
 }
 
-template <typename T, int NB, int N, int NT>
+template <typename T, int NB, int N, int NT, int PF = 4>
 __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb,
                                                      double* __restrict__ bands,
                                                      const int32_t* __restrict__ det_slot,
@@ -903,12 +939,16 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
   constexpr int HB = (HR - 1) > GR ? (HR - 1) : GR;    // back ghost depth
   constexpr int R = HR > GR ? HR : GR;                 // z ring half-width
   constexpr int P = NB + HF + HB;
+  constexpr int LPT = (P * P + NB * NB - 1) / (NB * NB);
+  constexpr int NP = NB / 2;
   __shared__ T pl[P * P];
   __shared__ double t1[P * NB];
   __shared__ Desc desc[27];
   __shared__ unsigned long long bmax[27];
   __shared__ int nonfinite;
-  const int b = first + blockIdx.x;
+  // XCD-aware order: a block's halo is its Morton neighbours' data, which
+  // then sits in the same XCD's L2
+  const int b = first + xcd_item(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   if (tid < 27) {
     make_desc(g, b, tid, desc[tid]);
@@ -917,63 +957,88 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
   if (tid == 0) nonfinite = 0;
   __syncthreads();
   const int tx = tid % NB, ty = tid / NB;
-  const int slot = det_slot ? det_slot[b] : -1;
-  double ring[2 * R + 1];
-#pragma unroll
-  for (int i = 0; i < 2 * R + 1; ++i) ring[i] = 0.0;
-  double mz[3] = {0.0, 0.0, 0.0};
+  const int slot = __builtin_amdgcn_readfirstlane(det_slot ? det_slot[b] : -1);
   const T* fbuf = g.field;
   const T* pbuf = g.patch;
-  auto load = [&](int x, int y, int z) -> T {
-    const int rx = x < 0 ? 0 : (x < NB ? 1 : 2);
-    const int ry = y < 0 ? 0 : (y < NB ? 1 : 2);
-    const int rz = z < 0 ? 0 : (z < NB ? 1 : 2);
-    const Desc d = desc[rx + 3 * ry + 9 * rz];
-    const T* buf = d.patch ? pbuf : fbuf;
-    return buf[d.off + x + (int64_t)y * d.sy + (int64_t)z * d.sz];
-  };
-  // input planes z = -HF .. NB+HB-1; output plane zo = zi - R once available.
-  // The next plane's values are loaded into registers while the current
-  // plane is transformed (software pipelining of the global loads).
-  constexpr int LPT = (P * P + NB * NB - 1) / (NB * NB);
-  // Two planes in flight with ping-pong register buffers: the buffer of plane
-  // zi is refilled with plane zi + 2 right after it is stored to LDS, so no
-  // register holding an outstanding load is ever copied (a copy would force
-  // a wait for the load).  The ring starts as zeros, which stand for the
-  // planes below -HF that no filter tap reaches.
-  // Every fetch issues exactly LPT loads (clamped indices, values past the
-  // plane or the last plane are never stored) so that the compiler can wait
-  // for a given plane with a partial vmcnt instead of draining all loads.
-  auto fetch = [&](T* dst, int z) {
-    const int zz = z < NB + HB - 1 ? z : NB + HB - 1;
+  // Each thread loads the same LPT positions (x, y) of every input plane
+  // (clamped onto the last position past the plane's end); their addresses
+  // are a pointer plus a z stride per slot, re-based when the fetched plane
+  // enters another z region (z < 0, [0, NB), >= NB).
+  const T* kp[LPT];
+  int32_t ksz[LPT];
+  int kx[LPT], ky[LPT];
+#pragma unroll
+  for (int k = 0; k < LPT; ++k) {
+    int i = tid + k * NB * NB;
+    i = i < P * P ? i : P * P - 1;
+    kx[k] = i % P - HF;
+    ky[k] = i / P - HF;
+  }
+  auto rebase = [&](int rz) {
 #pragma unroll
     for (int k = 0; k < LPT; ++k) {
-      int i = tid + k * NB * NB;
-      i = i < P * P ? i : P * P - 1;
-      dst[k] = load(i % P - HF, i / P - HF, zz);
+      const int rx = kx[k] < 0 ? 0 : (kx[k] < NB ? 1 : 2);
+      const int ry = ky[k] < 0 ? 0 : (ky[k] < NB ? 1 : 2);
+      const Desc d = desc[rx + 3 * ry + 9 * rz];
+      kp[k] = (d.patch ? pbuf : fbuf) + d.off + kx[k] + (int64_t)ky[k] * d.sy;
+      ksz[k] = d.sz;
     }
   };
-  auto body = [&](int zi, T* cur) {
-    const bool have = zi < NB + HB;
-    if (have) {
+  auto fetch = [&](T* dst, int z) {
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) dst[k] = kp[k][(int64_t)z * ksz[k]];
+  };
+  auto zreg = [](int z) { return z < 0 ? 0 : (z < NB ? 1 : 2); };
+  double ring[2 * R + 1];
+#pragma unroll
+  for (int i = 0; i < 2 * R + 1; ++i) ring[i] = 0.0;   // planes below -HF: no tap reaches them
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+  bool bad = false;
+  // PF planes in flight (a register ring); the whole plane loop is unrolled,
+  // so plane index, region changes, output parity and the ring rotations
+  // are resolved at compile time
+  constexpr int ZLAST = NB + HB - 1;   // last input plane
+  T nx[PF][LPT];
+#pragma unroll
+  for (int q = 0; q < PF; ++q) {
+    const int z = -HF + q;
+    if (z <= ZLAST) {
+      if (q == 0 || zreg(z) != zreg(z - 1)) rebase(zreg(z));
+      fetch(nx[q], z);
+    }
+  }
+#pragma unroll
+  for (int zi = -HF; zi < NB + R; ++zi) {
+    T* cur = nx[(zi + HF) % PF];
+    double v = 0.0;
+    if (zi <= ZLAST) {
 #pragma unroll
       for (int k = 0; k < LPT; ++k) {
         const int i = tid + k * NB * NB;
-        if (i < P * P) pl[i] = cur[k];
+        if (k < LPT - 1 || i < P * P) pl[i] = cur[k];
       }
-    }
-    __syncthreads();
-    if (have) {
-      fetch(cur, zi + 2);
-      for (int i = tid; i < P * NB; i += NB * NB) {
-        const int x = i % NB;       // output x
-        const int yy = i / NB;      // input y row (window index)
-        t1[i] = ana<N, NT>(pl + yy * P + x + HF, 1, x);  // FP64 from field precision
+      __syncthreads();
+      if (zi + PF <= ZLAST) {
+        if (zreg(zi + PF) != zreg(zi + PF - 1)) rebase(zreg(zi + PF));
+        fetch(cur, zi + PF);
       }
+      // x pass by pairs: H^a at the even point 2j, G^a at 2j+1 of each row
+      for (int i = tid; i < P * NP; i += NB * NB) {
+        const int j = i % NP, yy = i / NP;
+        const T* line = pl + yy * P + 2 * j + HF;
+        double ev = 0.0, od = 0.0;
+#pragma unroll
+        for (int o = -HR; o <= HR; ++o)
+          if (Ha<N, NT>::c(o) != 0.0) ev += Ha<N, NT>::c(o) * double(line[o]);
+#pragma unroll
+        for (int o = -GR; o <= GR; ++o)
+          if (Ga<N>::c(o) != 0.0) od += Ga<N>::c(o) * double(line[1 + o]);
+        t1[yy * NB + 2 * j] = ev;
+        t1[yy * NB + 2 * j + 1] = od;
+      }
+      __syncthreads();
+      v = ana<N, NT>(t1 + (ty + HF) * NB + tx, NB, ty);
     }
-    __syncthreads();
-    double v = 0.0;
-    if (have) v = ana<N, NT>(t1 + (ty + HF) * NB + tx, NB, ty);
 #pragma unroll
     for (int i = 0; i < 2 * R; ++i) ring[i] = ring[i + 1];
     ring[2 * R] = v;
@@ -989,25 +1054,19 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
         for (int o = -GR; o <= GR; ++o)
           if (Ga<N>::c(o) != 0.0) gsum += Ga<N>::c(o) * ring[R + o];
       }
-      const bool isdet = ((tx | ty | zo) & 1) != 0;
+      const bool isdet = (zo & 1) != 0 || ((tx | ty) & 1) != 0;
       const double a = isdet ? fabs(gsum) : 0.0;
-      if (!(a <= 1e300)) atomicAdd(&nonfinite, 1);
-      mz[0] = fmax(mz[0], a);
-      if (zo < eb) mz[1] = fmax(mz[1], a);
-      if (zo >= NB - ef) mz[2] = fmax(mz[2], a);
+      bad = bad || !(a <= 1e300);
+      m0 = fmax(m0, a);
+      if (zo < eb) m1 = fmax(m1, a);
+      if (zo >= NB - ef) m2 = fmax(m2, a);
       if (slot >= 0)
         det_out[(int64_t)slot * NB * NB * NB + ((int64_t)zo * NB + ty) * NB + tx] = isdet ? gsum : 0.0;
     }
-  };
-  T nx0[LPT], nx1[LPT];
-  fetch(nx0, -HF);
-  fetch(nx1, -HF + 1);
-  // the ring window is aligned so that output plane zo = zi - R
-  for (int zi = -HF; zi < NB + R; zi += 2) {
-    body(zi, nx0);
-    if (zi + 1 < NB + R) body(zi + 1, nx1);
   }
+  if (bad) atomicAdd(&nonfinite, 1);
   // fold into the 27 boxes that contain this column
+  const double mz[3] = {m0, m1, m2};
   const bool inx[3] = {true, tx < eb, tx >= NB - ef};
   const bool iny[3] = {true, ty < eb, ty >= NB - ef};
 #pragma unroll
