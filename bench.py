@@ -179,6 +179,8 @@ def main():
     ts = g.tree_stats()
     log("grid: %d leaves, levels %d..%d, %.3g points" %
         (n_blocks, ts[4], ts[3], n_blocks * cfg["nb"] ** 3))
+    log("ghost work per stage fill: %d values, %d c->f / substitution items (%d substitution), "
+        "%d f->c items, patch storage %d values" % (ts[1], ts[5], ts[2], ts[6], ts[9]))
 
     # -- headline: batched path, per-kernel HIP events around the launches
     g.prof_enable(True)

@@ -668,7 +668,7 @@ __global__ __launch_bounds__(256) void k_restrict(DevGrid<T> g, const RItem* __r
         for (int j = 0; j < XS; ++j) {
           const int jj = j < xs[n] ? j : xs[n] - 1;
           const int rn = jj < j0 ? 0 : (jj < j1 ? 1 : 2);
-          col[j] = sp[rn][(int64_t)jj * sst[rn]];
+          col[j] = sp[rn][jj * sst[rn]];
         }
       } else {
         // a finer-still leaf inside the window: resolve every point
