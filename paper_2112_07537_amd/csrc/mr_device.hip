@@ -408,6 +408,7 @@ __global__ __launch_bounds__(256) void k_gview(DevGrid<T> g, const GItem* __rest
   __shared__ int64_t cbase[64];
   __shared__ int32_t cstep[64];
   __shared__ uint8_t acell[3][32];
+  __shared__ int64_t roff[27];
   constexpr int J0 = 1 - N / 2;   // first DD tap offset
   constexpr int HN = N / 2 - 1;   // index of sample c inside the window
   const GItem it = items[xcd_item(blockIdx.x, gridDim.x)];
@@ -425,6 +426,7 @@ __global__ __launch_bounds__(256) void k_gview(DevGrid<T> g, const GItem* __rest
     e[a] = it.lo[a] & 1;   // 1: the first pair's even point is outside the box
   }
   sample_table<T, NB>(g, m, L, cbase, cstep, g.err);
+  if (tid >= 128 && tid < 128 + 27) roff[tid - 128] = g.poff[(int64_t)m * 27 + tid - 128];
   if (tid < 96) {
     const int a = tid >> 5, i = tid & 31;
     if (i < cs[a]) acell[a][i] = uint8_t((2 * (clo[a] + i) + NB / 2) / (NB / 2));
@@ -522,8 +524,20 @@ __global__ __launch_bounds__(256) void k_gview(DevGrid<T> g, const GItem* __rest
           }
           if (take) g.field[m * nb3 + (z * NB + y) * NB + x] = v;
         } else {
-          g.patch[it.off + ((int64_t)(z - it.rlo[2]) * it.rsz[1] + (y - it.rlo[1])) * it.rsz[0] +
-                  (x - it.rlo[0])] = v;
+          // region of the point and its place in that region's patch box
+          // (depth dw on the axes outside the block)
+          const int rx = x < 0 ? 0 : (x < NB ? 1 : 2);
+          const int ry = y < 0 ? 0 : (y < NB ? 1 : 2);
+          const int rz = z < 0 ? 0 : (z < NB ? 1 : 2);
+          const int r = rx + 3 * ry + 9 * rz;
+          if ((it.rmask >> r) & 1) {
+            const int dw = g.dw;
+            const int sx = rx == 1 ? NB : dw, sy = ry == 1 ? NB : dw;
+            const int lx = x + (rx == 0 ? dw : (rx == 1 ? 0 : -NB));
+            const int ly = y + (ry == 0 ? dw : (ry == 1 ? 0 : -NB));
+            const int lz = z + (rz == 0 ? dw : (rz == 1 ? 0 : -NB));
+            g.patch[roff[r] + (lz * sy + ly) * sx + lx] = v;
+          }
         }
       }
     }

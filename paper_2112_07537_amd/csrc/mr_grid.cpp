@@ -333,28 +333,16 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
       int rlo[3], rhi[3], blo[3], bhi[3];
       region_box(nb, Dw, r, rlo, rhi);
       if (lr < Lb) {
-        // c->f patch of this region, depth Dc
-        GItem pt{};
-        pt.blk = b;
-        pt.sel = Nt ? 8 : 0;
-        for (int a = 0; a < 3; ++a)
-          if (rr[a] != 1) pt.sel |= (1 << a);
-        region_box(nb, Dc, r, blo, bhi);
-        pt.off = g->poff[size_t(b) * 27 + r];
-        for (int a = 0; a < 3; ++a) {
-          pt.lo[a] = blo[a];
-          pt.hi[a] = bhi[a];
-          pt.rlo[a] = rlo[a];
-          pt.rsz[a] = rhi[a] - rlo[a];
-        }
-        L.out_points += box_size(blo, bhi);
-        push_tiled(L.g, pt, glds);
+        // c->f patches are merged per side below
         // substitution slab of this interface (READING R-SUB), unless a
         // coarser region facing a proper subset of the same axes exists: its
         // slab contains this one (and the substituted values do not depend
         // on which item computes them)
-        GItem sb = pt;
-        sb.sel |= 16;
+        GItem sb{};
+        sb.blk = b;
+        sb.sel = (Nt ? 8 : 0) | 16;
+        for (int a = 0; a < 3; ++a)
+          if (rr[a] != 1) sb.sel |= (1 << a);
         bool sempty = false;
         for (int a = 0; a < 3; ++a) {
           const int d = rr[a] - 1;
@@ -412,6 +400,39 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
             }
       }
     }
+    // c->f patches, merged per side: a coarser region goes to the side of
+    // its lowest facing axis; the item's box is the bounding box of the
+    // side's regions at depth Dc, and only those regions are written
+    for (int a = 0; a < 3; ++a)
+      for (int side = 0; side <= 2; side += 2) {
+        GItem pt{};
+        pt.blk = b;
+        pt.sel = Nt ? 8 : 0;
+        int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+        for (int r = 0; r < 27; ++r) {
+          if (r == 13) continue;
+          const int rr[3] = {r % 3, (r / 3) % 3, r / 9};
+          int low = -1;
+          for (int c = 2; c >= 0; --c)
+            if (rr[c] != 1) low = c;
+          if (low != a || rr[a] != side) continue;
+          if (region_level(g, b, r) >= Lb) continue;
+          int blo[3], bhi[3];
+          region_box(nb, Dc, r, blo, bhi);
+          for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], blo[c]);
+            hi[c] = std::max(hi[c], bhi[c]);
+          }
+          pt.rmask |= 1 << r;
+          L.out_points += box_size(blo, bhi);
+        }
+        if (!pt.rmask) continue;
+        for (int c = 0; c < 3; ++c) {
+          pt.lo[c] = lo[c];
+          pt.hi[c] = hi[c];
+        }
+        push_tiled(L.g, pt, glds);
+      }
   }
   // sample boxes of c->f and substitution items must stay inside the map,
   // and their extent fits the kernel's per-axis cell table (32 samples)

@@ -11,20 +11,20 @@ namespace mr {
 
 // Zero-detail refinement of a box (coarse-extension assumption, section
 // 2.2.2): the tensor Deslauriers-Dubuc refinement of the level-(L-1) samples
-// around a box of level-L points of block blk.  A patch item writes the c->f
-// ghost values of one region of blk into blk's patch; a substitution item
+// around a box of level-L points of block blk.  A patch item covers the
+// coarser regions of blk on one side (bit r of rmask set for region r);
+// each point is written into the patch of its region.  A substitution item
 // overwrites the points of blk's slab next to a coarser leaf that pass the
 // selector (section 2.2.4).
 struct GItem {
   int32_t blk;      // fine block whose owner map resolves the samples
-  int32_t sel;      // bits 0..2 = axes facing the coarser leaf,
+  int32_t sel;      // bits 0..2 = axes facing the coarser leaf (substitution),
                     // bit 3 = lifted wavelet (every non-all-even point),
                     // bit 4 = substitution item (else patch item)
   int32_t lo[3];    // box [lo, hi) of level-L points, relative to blk's
   int32_t hi[3];    //   origin at blk's level
-  int32_t rlo[3];   // patch region origin / extent (output indexing)
-  int32_t rsz[3];
-  int64_t off;      // patch offset
+  int32_t rmask;    // patch item: regions (rx + 3 ry + 9 rz) written
+  int32_t pad;
 };
 
 // Restriction of finer data to coarse ghost points (f->c, ghosting Part 2):
