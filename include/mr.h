@@ -26,8 +26,9 @@
  *    the call.  Device memory is owned by the library (hipMalloc) and freed
  *    by mr_grid_destroy.
  *  - Streams: device work is issued on the hipStream_t given at creation;
- *    with NULL the library creates a private non-blocking stream.  mr_ghost, mr_rk3_step and mr_details with
- *    on_device = 1 are asynchronous; every other call synchronises the stream.
+ *    with NULL the library creates a private non-blocking stream.  mr_ghost,
+ *    mr_rk3_step and mr_details with on_device = 1 are asynchronous; every
+ *    other call synchronises the stream.
  *  - A grid handle is not thread-safe.
  */
 #ifndef MR_H
@@ -56,7 +57,11 @@ typedef enum { MR_F64 = 0, MR_F32 = 1 } mr_prec;
 
 /* Grid configuration (section 2.2 and the adaptation supplement). */
 typedef struct {
-  int32_t nb;          /* points per block edge: 8, 16 or 24               */
+  int32_t nb;          /* points per block edge: 8, 16 or 24.  The samples
+                          of a ghost reconstruction must stay within half a
+                          block around the block: nb = 8 takes N = 2 only,
+                          nb = 16 takes N <= 4, nb = 24 every wavelet
+                          (else MR_EINVAL at creation)                      */
   int32_t wavelet_N;   /* interpolation order N: 2, 4 or 6                  */
   int32_t wavelet_Nt;  /* vanishing moments Nt: 0 (Donoho) or 2 (lifted)    */
   int32_t fd_order;    /* central first-derivative order: 4 or 6            */
@@ -144,7 +149,9 @@ mr_status mr_ghost_get(mr_grid* g, int32_t field, int32_t depth, int64_t b0,
  * transform (x, y, z), per-block max |gamma| (FP64).  norms: n_blocks
  * doubles, host (on_device = 0, synchronises) or device (on_device = 1);
  * with on_device = 1, norms may be NULL: the norms stay in the library's
- * device buffer (asynchronous). */
+ * device buffer (asynchronous).  With on_device = 0 a NaN or infinite norm
+ * (non-finite field values) returns MR_ENONFINITE after the norms are
+ * written; mr_adapt returns the same before changing the tree. */
 mr_status mr_details(mr_grid* g, int32_t field, double* norms, int32_t on_device);
 
 /* Iterative adaptation (adaptation supplement): criterion, flags, policy
