@@ -955,8 +955,9 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
   constexpr int P = NB + HF + HB;
   constexpr int LPT = (P * P + NB * NB - 1) / (NB * NB);
   constexpr int NP = NB / 2;
-  __shared__ T pl[P * P];
-  __shared__ double t1[P * NB];
+  __shared__ double pl[P * P];      // input plane, converted once to FP64
+  __shared__ double t1[P * NB];     // after the x pass
+  __shared__ double t2[NB * NB];    // after the y pass
   __shared__ Desc desc[27];
   __shared__ unsigned long long bmax[27];
   __shared__ int nonfinite;
@@ -1029,7 +1030,7 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
 #pragma unroll
       for (int k = 0; k < LPT; ++k) {
         const int i = tid + k * NB * NB;
-        if (k < LPT - 1 || i < P * P) pl[i] = cur[k];
+        if (k < LPT - 1 || i < P * P) pl[i] = double(cur[k]);
       }
       __syncthreads();
       if (zi + PF <= ZLAST) {
@@ -1039,19 +1040,34 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
       // x pass by pairs: H^a at the even point 2j, G^a at 2j+1 of each row
       for (int i = tid; i < P * NP; i += NB * NB) {
         const int j = i % NP, yy = i / NP;
-        const T* line = pl + yy * P + 2 * j + HF;
+        const double* line = pl + yy * P + 2 * j + HF;
         double ev = 0.0, od = 0.0;
 #pragma unroll
         for (int o = -HR; o <= HR; ++o)
-          if (Ha<N, NT>::c(o) != 0.0) ev += Ha<N, NT>::c(o) * double(line[o]);
+          if (Ha<N, NT>::c(o) != 0.0) ev += Ha<N, NT>::c(o) * line[o];
 #pragma unroll
         for (int o = -GR; o <= GR; ++o)
-          if (Ga<N>::c(o) != 0.0) od += Ga<N>::c(o) * double(line[1 + o]);
+          if (Ga<N>::c(o) != 0.0) od += Ga<N>::c(o) * line[1 + o];
         t1[yy * NB + 2 * j] = ev;
         t1[yy * NB + 2 * j + 1] = od;
       }
       __syncthreads();
-      v = ana<N, NT>(t1 + (ty + HF) * NB + tx, NB, ty);
+      // y pass by pairs: column x, rows 2j (H^a) and 2j+1 (G^a)
+      if (tid < NB * NP) {
+        const int x = tid % NB, j = tid / NB;
+        const double* col = t1 + (2 * j + HF) * NB + x;
+        double ev = 0.0, od = 0.0;
+#pragma unroll
+        for (int o = -HR; o <= HR; ++o)
+          if (Ha<N, NT>::c(o) != 0.0) ev += Ha<N, NT>::c(o) * col[o * NB];
+#pragma unroll
+        for (int o = -GR; o <= GR; ++o)
+          if (Ga<N>::c(o) != 0.0) od += Ga<N>::c(o) * col[(1 + o) * NB];
+        t2[2 * j * NB + x] = ev;
+        t2[(2 * j + 1) * NB + x] = od;
+      }
+      __syncthreads();
+      v = t2[ty * NB + tx];
     }
 #pragma unroll
     for (int i = 0; i < 2 * R; ++i) ring[i] = ring[i + 1];
