@@ -207,14 +207,17 @@ def main():
     # -- adaptation amortised (second loop, same grid)
     extra = {}
     if cfg.get("adapt_every"):
+        g.prof_enable(False)   # clears the host phase timers
         ta_t, ta_pts, t_adapt, n_adapt = timed_steps(g, cfg, max(args.steps, cfg["adapt_every"]),
                                                      0, adapt_every=cfg["adapt_every"])
         extra["with_adapt_points_per_s"] = ta_pts / ta_t
         extra["adapt_ms_each"] = 1e3 * t_adapt / max(1, n_adapt)
         extra["adapt_every"] = cfg["adapt_every"]
-        log("with adapt every %d: %.4g points/s, %.1f ms per adaptation, %d leaves" %
+        extra["adapt_phase_ms"] = {k: round(g.prof_read(k)[0] / max(1, n_adapt), 2) for k in
+                                   ("adapt_criterion", "adapt_plan", "adapt_apply", "tree_commit")}
+        log("with adapt every %d: %.4g points/s, %.1f ms per adaptation, %d leaves; phases %s" %
             (cfg["adapt_every"], extra["with_adapt_points_per_s"], extra["adapt_ms_each"],
-             g.n_blocks()))
+             g.n_blocks(), extra["adapt_phase_ms"]))
 
     cpu = None
     if not args.no_cpu:

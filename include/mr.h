@@ -191,7 +191,10 @@ mr_status mr_moments(mr_grid* g, int32_t field, double out[4]);
  * launch of the named kernel family ("rhs", "details", "ghost_refine",
  * "ghost_restrict").  mr_prof_enable(g, 1) clears and starts recording;
  * mr_prof_read synchronises and returns the summed milliseconds, the number
- * of launches and the points processed per launch. */
+ * of launches and the points processed per launch.  The names
+ * "adapt_criterion", "adapt_plan", "adapt_apply" and "tree_commit" return
+ * the host wall-clock time of those phases of mr_adapt / tree changes and
+ * their count (always recorded; cleared by mr_prof_enable). */
 mr_status mr_prof_enable(mr_grid* g, int32_t on);
 mr_status mr_prof_read(mr_grid* g, const char* kernel, double* total_ms, int64_t* launches,
                        int64_t* points_per_launch);

@@ -9,10 +9,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <unordered_set>
 #include <vector>
@@ -57,6 +60,43 @@ static inline uint64_t morton(const Key& b) {
          (spread3(uint64_t(b.k) << s) << 2);
 }
 
+// Leaf key -> block index: open addressing with linear probing (the map is
+// rebuilt after every tree change and queried a few million times then).
+struct LeafIndex {
+  static constexpr uint64_t kEmpty = ~0ull;
+  std::vector<uint64_t> keys;
+  std::vector<int32_t> vals;
+  uint64_t mask = 0;
+  static uint64_t mix(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    return x;
+  }
+  void build(size_t n) {
+    size_t cap = 16;
+    while (cap < 2 * n + 16) cap <<= 1;
+    keys.assign(cap, kEmpty);
+    vals.assign(cap, -1);
+    mask = cap - 1;
+  }
+  void insert(uint64_t key, int32_t v) {
+    uint64_t h = mix(key) & mask;
+    while (keys[h] != kEmpty && keys[h] != key) h = (h + 1) & mask;
+    keys[h] = key;
+    vals[h] = v;
+  }
+  int32_t find(uint64_t key) const {
+    if (keys.empty()) return -1;
+    uint64_t h = mix(key) & mask;
+    while (keys[h] != kEmpty) {
+      if (keys[h] == key) return vals[h];
+      h = (h + 1) & mask;
+    }
+    return -1;
+  }
+};
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -98,6 +138,19 @@ struct Prof {
 
 static const char* kFam[4] = {"rhs", "details", "ghost_refine", "ghost_restrict"};
 
+// Host-side phases of an adaptation (wall clock, stream work included where
+// the phase waits for it): criterion (ghosts + transform + norms to host),
+// plan (flags + policy), apply (refine / coarsen / update passes), commit
+// (owner map, patch offsets, work lists, uploads).
+static const char* kHostPhase[4] = {"adapt_criterion", "adapt_plan", "adapt_apply", "tree_commit"};
+struct HostTimer {
+  double ms[4] = {0, 0, 0, 0};
+  int64_t n[4] = {0, 0, 0, 0};
+};
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 }  // namespace mr
 
 using namespace mr;
@@ -106,13 +159,14 @@ struct mr_grid {
   mr_config cfg{};
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  HostTimer htime;
   bool f32 = false;
   int nb = 16, N = 4, Nt = 0, G = 2, Dw = 4;
   int Ef = 0, Eb = 0;
   size_t esz = 8;
   // tree
   std::vector<Key> leaves;
-  std::unordered_map<uint64_t, int32_t> index;
+  LeafIndex index;
   std::vector<int32_t> cmap;
   std::vector<int64_t> poff;
   int64_t patch_elems = 0;
@@ -141,8 +195,7 @@ static int find_leaf(const mr_grid* g, int L, int i, int j, int k) {
   i = ((i % n) + n) % n;
   j = ((j % n) + n) % n;
   k = ((k % n) + n) % n;
-  auto it = g->index.find(pack(L, i, j, k));
-  return it == g->index.end() ? -1 : it->second;
+  return g->index.find(pack(L, i, j, k));
 }
 
 // Leaf containing the level-Lc cell (I, J, K) (periodic), searching the cell
@@ -183,35 +236,85 @@ static int neighbor_kind(const mr_grid* g, int b, int dx, int dy, int dz, int* i
 }
 
 static void rebuild_index(mr_grid* g) {
-  g->index.clear();
-  g->index.reserve(g->leaves.size() * 2);
+  g->index.build(g->leaves.size());
   for (size_t b = 0; b < g->leaves.size(); ++b) {
     const Key& k = g->leaves[b];
-    g->index[pack(k.L, k.i, k.j, k.k)] = int32_t(b);
+    g->index.insert(pack(k.L, k.i, k.j, k.k), int32_t(b));
   }
 }
 
 static void sort_leaves(std::vector<Key>& v) {
-  std::sort(v.begin(), v.end(), [](const Key& a, const Key& b) { return morton(a) < morton(b); });
+  std::vector<std::pair<uint64_t, Key>> t(v.size());
+  for (size_t i = 0; i < v.size(); ++i) t[i] = {morton(v[i]), v[i]};
+  std::sort(t.begin(), t.end(), [](const std::pair<uint64_t, Key>& a, const std::pair<uint64_t, Key>& b) {
+    return a.first < b.first;
+  });
+  for (size_t i = 0; i < v.size(); ++i) v[i] = t[i].second;
 }
 
 // Owner map (4x4x4 half-block cells around each block) and 2:1 check.
+// Run body(lo, hi) over [0, n) split into contiguous chunks on host threads.
+template <typename F>
+static void parallel_for(size_t n, F body) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const unsigned nt = std::min<unsigned>(16, hw);
+  if (n < 2 || nt == 1) {
+    body(size_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const size_t chunk = (n + nt - 1) / nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    const size_t lo = t * chunk, hi = std::min(n, lo + chunk);
+    if (lo >= hi) break;
+    th.emplace_back(body, lo, hi);
+  }
+  for (auto& x : th) x.join();
+}
+
+// Owner map (4x4x4 half-block cells around each block) and 2:1 check.  The
+// cells of one of the 27 regions around a block share the owner unless the
+// region is subdivided, so each region costs one or two lookups.
 static mr_status build_cmap(mr_grid* g) {
   const size_t n = g->leaves.size();
   g->cmap.assign(n * 64, -1);
-  for (size_t b = 0; b < n; ++b) {
-    const Key& k = g->leaves[b];
-    for (int cz = 0; cz < 4; ++cz)
-      for (int cy = 0; cy < 4; ++cy)
-        for (int cx = 0; cx < 4; ++cx) {
-          const int I = 2 * k.i + cx - 1, J = 2 * k.j + cy - 1, K = 2 * k.k + cz - 1;
-          const int id = leaf_containing(g, k.L + 1, I, J, K);
-          if (id < 0 || std::abs(g->leaves[id].L - k.L) > 1)
-            return fail(MR_EINVAL, "tree is not 2:1 balanced around block (" + std::to_string(k.L) +
-                                       "," + std::to_string(k.i) + "," + std::to_string(k.j) +
-                                       "," + std::to_string(k.k) + ")");
-          g->cmap[b * 64 + (cz * 4 + cy) * 4 + cx] = id;
+  std::atomic<int64_t> bad{-1};
+  parallel_for(n, [&](size_t lo, size_t hi) {
+    for (size_t b = lo; b < hi; ++b) {
+      const Key& k = g->leaves[b];
+      for (int r = 0; r < 27; ++r) {
+        const int rr[3] = {r % 3, (r / 3) % 3, r / 9};
+        int id = find_leaf(g, k.L, k.i + rr[0] - 1, k.j + rr[1] - 1, k.k + rr[2] - 1);
+        if (id < 0 && k.L > 0) {
+          const int m = 1 << k.L;
+          const int ii = ((k.i + rr[0] - 1) % m + m) % m, jj = ((k.j + rr[1] - 1) % m + m) % m,
+                    kk = ((k.k + rr[2] - 1) % m + m) % m;
+          id = find_leaf(g, k.L - 1, ii >> 1, jj >> 1, kk >> 1);
         }
+        const int c0[3] = {rr[0] == 0 ? 0 : (rr[0] == 1 ? 1 : 3), rr[1] == 0 ? 0 : (rr[1] == 1 ? 1 : 3),
+                           rr[2] == 0 ? 0 : (rr[2] == 1 ? 1 : 3)};
+        const int c1[3] = {rr[0] == 1 ? 2 : c0[0], rr[1] == 1 ? 2 : c0[1], rr[2] == 1 ? 2 : c0[2]};
+        for (int cz = c0[2]; cz <= c1[2]; ++cz)
+          for (int cy = c0[1]; cy <= c1[1]; ++cy)
+            for (int cx = c0[0]; cx <= c1[0]; ++cx) {
+              int cid = id;
+              if (cid < 0)   // subdivided (or not 2:1): resolve the cell itself
+                cid = leaf_containing(g, k.L + 1, 2 * k.i + cx - 1, 2 * k.j + cy - 1, 2 * k.k + cz - 1);
+              if (cid < 0 || std::abs(g->leaves[cid].L - k.L) > 1) {
+                int64_t expect = -1;
+                bad.compare_exchange_strong(expect, int64_t(b));
+                cid = -1;
+              }
+              g->cmap[b * 64 + (cz * 4 + cy) * 4 + cx] = cid;
+            }
+      }
+    }
+  });
+  if (bad.load() >= 0) {
+    const Key& k = g->leaves[size_t(bad.load())];
+    return fail(MR_EINVAL, "tree is not 2:1 balanced around block (" + std::to_string(k.L) + "," +
+                               std::to_string(k.i) + "," + std::to_string(k.j) + "," +
+                               std::to_string(k.k) + ")");
   }
   return MR_OK;
 }
@@ -323,7 +426,15 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
   auto rlds = [&](const RItem& it) { return rview_lds(it, H, esz); };
   const int n = int(g->leaves.size());
   const int hb = nb / 2;
-  for (int b = 0; b < n; ++b) {
+  // blocks are split into contiguous chunks built on host threads; the
+  // chunks' items are concatenated in block order
+  struct Part {
+    std::vector<GItem> g;
+    std::vector<RItem> r;
+    int64_t pts = 0;
+    bool ok = true;
+  };
+  auto one_block = [&](int b, Part& P) -> bool {
     const int Lb = g->leaves[b].L;
     for (int r = 0; r < 27; ++r) {
       if (r == 13) continue;
@@ -365,7 +476,7 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
           for (int a = 0; a < 3; ++a, mul *= 3) r2 += mul * ((sub >> a) & 1 ? rr[a] : 1);
           if (region_level(g, b, r2) < Lb) covered = true;
         }
-        if (!sempty && !covered) push_tiled(L.g, sb, glds);
+        if (!sempty && !covered) push_tiled(P.g, sb, glds);
       } else {
         // f->c: each finer leaf covering this region restricts its part
         region_box(nb, D, r, blo, bhi);
@@ -394,9 +505,9 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
               }
               if (empty) continue;
               if (g->leaves[it.fblk].L != Lb + 1)
-                return fail(MR_EINVAL, "finer region not covered by level+1 leaves");
-              L.out_points += box_size(it.lo, it.hi);
-              push_tiled(L.r, it, rlds);
+                return false;
+              P.pts += box_size(it.lo, it.hi);
+              push_tiled(P.r, it, rlds);
             }
       }
     }
@@ -424,15 +535,30 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
             hi[c] = std::max(hi[c], bhi[c]);
           }
           pt.rmask |= 1 << r;
-          L.out_points += box_size(blo, bhi);
+          P.pts += box_size(blo, bhi);
         }
         if (!pt.rmask) continue;
         for (int c = 0; c < 3; ++c) {
           pt.lo[c] = lo[c];
           pt.hi[c] = hi[c];
         }
-        push_tiled(L.g, pt, glds);
+        push_tiled(P.g, pt, glds);
       }
+      return true;
+  };
+  const int nchunk = std::max(1, std::min(64, n / 256));
+  std::vector<Part> parts(nchunk);
+  parallel_for(size_t(nchunk), [&](size_t c0, size_t c1) {
+    for (size_t c = c0; c < c1; ++c) {
+      const int lo = int(int64_t(n) * int64_t(c) / nchunk), hi = int(int64_t(n) * int64_t(c + 1) / nchunk);
+      for (int b = lo; b < hi && parts[c].ok; ++b) parts[c].ok = one_block(b, parts[c]);
+    }
+  });
+  for (Part& P : parts) {
+    if (!P.ok) return fail(MR_EINVAL, "finer region not covered by level+1 leaves");
+    L.g.insert(L.g.end(), P.g.begin(), P.g.end());
+    L.r.insert(L.r.end(), P.r.begin(), P.r.end());
+    L.out_points += P.pts;
   }
   // sample boxes of c->f and substitution items must stay inside the map,
   // and their extent fits the kernel's per-axis cell table (32 samples)
@@ -460,7 +586,16 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
 }
 
 // Upload tree metadata and rebuild every derived structure.
+static mr_status commit_tree_impl(mr_grid* g);
 static mr_status commit_tree(mr_grid* g) {
+  const double t0 = now_ms();
+  mr_status st = commit_tree_impl(g);
+  g->htime.ms[3] += now_ms() - t0;
+  g->htime.n[3] += 1;
+  return st;
+}
+
+static mr_status commit_tree_impl(mr_grid* g) {
   rebuild_index(g);
   mr_status st = build_cmap(g);
   if (st != MR_OK) return st;
@@ -737,10 +872,11 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
                             bool resample_only) {
   const int n_old = int(g->leaves.size());
   const int nb = g->nb;
-  std::unordered_set<uint64_t> coarsen_child;
+  LeafIndex coarsen_child;   // children of the coarsened parents -> 1
+  coarsen_child.build(8 * plan.parents.size());
   for (const Key& p : plan.parents)
     for (int c = 0; c < 8; ++c)
-      coarsen_child.insert(pack(p.L + 1, 2 * p.i + (c & 1), 2 * p.j + ((c >> 1) & 1), 2 * p.k + ((c >> 2) & 1)));
+      coarsen_child.insert(pack(p.L + 1, 2 * p.i + (c & 1), 2 * p.j + ((c >> 1) & 1), 2 * p.k + ((c >> 2) & 1)), 1);
   std::vector<Key> nl;
   nl.reserve(n_old + 7 * plan.refined);
   for (int b = 0; b < n_old; ++b) {
@@ -748,7 +884,7 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
     if (plan.refine[b]) {
       for (int c = 0; c < 8; ++c)
         nl.push_back({k.L + 1, 2 * k.i + (c & 1), 2 * k.j + ((c >> 1) & 1), 2 * k.k + ((c >> 2) & 1)});
-    } else if (!coarsen_child.count(pack(k.L, k.i, k.j, k.k))) {
+    } else if (coarsen_child.find(pack(k.L, k.i, k.j, k.k)) < 0) {
       nl.push_back(k);
     }
   }
@@ -757,8 +893,9 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
     return fail(MR_ECAPACITY, "adaptation needs " + std::to_string(nl.size()) + " blocks, capacity " +
                                   std::to_string(g->cfg.max_blocks));
   sort_leaves(nl);
-  std::unordered_map<uint64_t, int32_t> nidx;
-  for (size_t i = 0; i < nl.size(); ++i) nidx[pack(nl[i].L, nl[i].i, nl[i].j, nl[i].k)] = int32_t(i);
+  LeafIndex nidx;
+  nidx.build(nl.size());
+  for (size_t i = 0; i < nl.size(); ++i) nidx.insert(pack(nl[i].L, nl[i].i, nl[i].j, nl[i].k), int32_t(i));
   if (created)
     for (int b = 0; b < n_old; ++b)
       if (plan.refine[b]) {
@@ -782,7 +919,18 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
     int nslot = 0;
     for (int b = 0; b < n_old; ++b) {
       const Key& k = g->leaves[b];
-      if (coarsen_child.count(pack(k.L, k.i, k.j, k.k))) slot[b] = nslot++;
+      if (coarsen_child.find(pack(k.L, k.i, k.j, k.k)) >= 0) slot[b] = nslot++;
+    }
+    // kept blocks with a same-level neighbour in a coarsening sibling set
+    std::vector<char> touches(n_old, 0);
+    for (int b = 0; b < n_old; ++b) {
+      if (slot[b] < 0) continue;
+      const Key& k = g->leaves[b];
+      for (int r = 0; r < 27; ++r) {
+        if (r == 13) continue;
+        const int id = find_leaf(g, k.L, k.i + r % 3 - 1, k.j + (r / 3) % 3 - 1, k.k + r / 9 - 1);
+        if (id >= 0 && slot[id] < 0) touches[id] = 1;
+      }
     }
     const int H = Hreach(g->N, g->Nt);
     for (int b = 0; b < n_old; ++b) {
@@ -791,7 +939,7 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
       if (plan.refine[b]) {
         for (int c = 0; c < 8; ++c) {
           const int o[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
-          const int child = nidx[pack(k.L + 1, 2 * k.i + o[0], 2 * k.j + o[1], 2 * k.k + o[2])];
+          const int child = nidx.find(pack(k.L + 1, 2 * k.i + o[0], 2 * k.j + o[1], 2 * k.k + o[2]));
           int flo[3], fhi[3], clo[3], chi[3];
           for (int a = 0; a < 3; ++a) {
             flo[a] = o[a] * nb;
@@ -820,9 +968,9 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
           scr += box_size(b1lo, b1hi);
           add3(ref, p0, p1, p2);
         }
-      } else if (coarsen_child.count(key)) {
+      } else if (coarsen_child.find(key) >= 0) {
         const int o[3] = {k.i & 1, k.j & 1, k.k & 1};
-        const int parent = nidx[pack(k.L - 1, k.i >> 1, k.j >> 1, k.k >> 1)];
+        const int parent = nidx.find(pack(k.L - 1, k.i >> 1, k.j >> 1, k.k >> 1));
         const int hb = nb / 2;
         const int b0lo[3] = {0, -H, -H}, b0hi[3] = {hb, nb - 1 + H, nb - 1 + H};
         const int b1lo[3] = {0, 0, -H}, b1hi[3] = {hb, hb, nb - 1 + H};
@@ -846,20 +994,12 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
         scr += box_size(b1lo, b1hi);
         add3(crs, p0, p1, p2);
       } else {
-        const int nid = nidx[key];
+        const int nid = nidx.find(key);
         pairs.push_back(nid);
         pairs.push_back(b);
         // update step on kept blocks next to a coarsening sibling set of
         // their own level (Table 3, update after neighbour has coarsened)
-        bool touches = false;
-        for (int dz = -1; dz <= 1 && !touches; ++dz)
-          for (int dy = -1; dy <= 1 && !touches; ++dy)
-            for (int dx = -1; dx <= 1 && !touches; ++dx) {
-              if (!dx && !dy && !dz) continue;
-              int id;
-              if (neighbor_kind(g, b, dx, dy, dz, &id) == 0 && slot[id] >= 0) touches = true;
-            }
-        if (touches && !plan.parents.empty()) {
+        if (touches[b]) {
           int r = 0;
           const int Jr = g->Nt ? 1 : 0, Kr = g->Nt ? g->N : g->N - 1;
           r = std::max(Jr, Kr);
@@ -964,28 +1104,37 @@ static mr_status norms_to_host(mr_grid* g, int field, std::vector<double>& out) 
 static mr_status adapt_impl(mr_grid* g, int field, int max_iter, mr_adapt_stats* stats) {
   std::unordered_set<uint64_t> created;
   mr_adapt_stats s{};
-  // transactional: keep copies of the tree and fields until success
-  std::vector<Key> saved = g->leaves;
+  // an iteration is applied whole or not at all; earlier iterations remain
+  HostTimer& ht = g->htime;
   for (int it = 0; it < max_iter; ++it) {
     std::vector<double> norms;
+    double t0 = now_ms();
     mr_status st = norms_to_host(g, field, norms);
+    ht.ms[0] += now_ms() - t0;
+    ht.n[0] += 1;
     if (st != MR_OK) return st;
     Plan plan;
     int band = 0;
+    t0 = now_ms();
     make_plan(g, norms, created, true, plan, &band);
+    ht.ms[1] += now_ms() - t0;
+    ht.n[1] += 1;
     s.in_band = band;
     if (plan.refined == 0 && plan.coarsened == 0) break;
     int64_t nn = int64_t(g->leaves.size()) + 7 * int64_t(plan.refined) - 7 * int64_t(plan.coarsened);
     if (nn > g->cfg.max_blocks)
       return fail(MR_ECAPACITY, "adaptation needs " + std::to_string(nn) + " blocks, capacity " +
                                     std::to_string(g->cfg.max_blocks));
+    t0 = now_ms();
+    const double c0 = ht.ms[3];
     st = apply_plan(g, plan, &created, false);
+    ht.ms[2] += now_ms() - t0 - (ht.ms[3] - c0);   // the commit is timed on its own
+    ht.n[2] += 1;
     if (st != MR_OK) return st;
     s.iters++;
     s.refined += plan.refined;
     s.coarsened += plan.coarsened;
   }
-  (void)saved;
   s.n_blocks = int64_t(g->leaves.size());
   if (stats) *stats = s;
   return MR_OK;
@@ -1371,6 +1520,7 @@ mr_status mr_prof_enable(mr_grid* g, int32_t on) {
   }
   g->prof.recs.clear();
   g->prof.on = on != 0;
+  g->htime = HostTimer{};
   return MR_OK;
 }
 
@@ -1380,6 +1530,13 @@ mr_status mr_prof_read(mr_grid* g, const char* kernel, double* total_ms, int64_t
   int fam = -1;
   for (int f = 0; f < 4; ++f)
     if (std::strcmp(kernel, kFam[f]) == 0) fam = f;
+  for (int f = 0; f < 4; ++f)
+    if (std::strcmp(kernel, kHostPhase[f]) == 0) {
+      *total_ms = g->htime.ms[f];
+      *launches = g->htime.n[f];
+      if (points_per_launch) *points_per_launch = 0;
+      return MR_OK;
+    }
   if (fam < 0) return fail(MR_EINVAL, "unknown kernel family");
   HIPCHK(hipStreamSynchronize(g->stream));
   double ms = 0;
