@@ -106,6 +106,37 @@ def test_fullsize_ghost_and_details_sampled(fullsize):
         assert abs(nrm[b] - ref) <= tol * 4, (keys[b], nrm[b], ref)
 
 
+def test_fullsize_flags_sampled(fullsize):
+    """Detail norms and refine/coarsen flags of sampled blocks at the bench
+    size, GPU against the FP64 oracle evaluated on the GPU's ghost-filled
+    field.  Norms agree within the FP32 contract (1e-5 of max|phi|); flags
+    agree except for blocks whose oracle norm lies within 1e-4 relative of a
+    threshold or within the FP32 rounding of the ghost values (2e-7 of
+    max|phi|, about three units of FP32 roundoff)."""
+    cfg, g = fullsize
+    keys = [tuple(int(v) for v in m) for m in g.block_meta()]
+    nrm = g.details()                      # ghost fill (substitution) + transform
+    data = g.field_get().astype(np.float64)
+    o = oracle_of(g, cfg, keys, data)
+    scale = np.abs(data).max()
+    rng = np.random.default_rng(11)
+    picks = rng.choice(len(keys), size=150, replace=False)
+    det = {}
+    er, ec = cfg["eps_refine"], cfg["eps_coarsen"]
+    mismatches = 0
+    for b in picks:
+        ref = o.block_norm(keys[b], det)
+        assert abs(nrm[b] - ref) <= 1e-5 * scale, (keys[b], nrm[b], ref)
+        L = keys[b][0]
+        fg = (nrm[b] >= er and L < cfg["level_max"], nrm[b] <= ec and L > cfg["level_min"])
+        fo = (ref >= er and L < cfg["level_max"], ref <= ec and L > cfg["level_min"])
+        if fg != fo:
+            band = min(abs(ref - er) - 1e-4 * er, abs(ref - ec) - 1e-4 * ec)
+            assert band <= 2e-7 * scale, (keys[b], nrm[b], ref)
+            mismatches += 1
+    assert mismatches <= len(picks) // 10
+
+
 def test_fullsize_fp32_step_vs_fp64(fullsize):
     cfg, g = fullsize
     keys = g.block_meta()
