@@ -1375,22 +1375,29 @@ void launch_gview(bool f32, const void* dg, Wavelet w, const GItem* items, int n
   else gview_t<double>(dg, w, items, n, lds, s);
 }
 
+// MAXQ bounds the coarse points per column of pass 1 (the item's thinnest
+// extent): 3 covers stencil-depth fills up to FD6, 6 the widest fills.
 template <typename T, int NB>
-static void rview_nb(const DevGrid<T>& g, Wavelet w, const RItem* items, int n, int lds, hipStream_t s) {
-  MR_WAVELET_SWITCH(w, MR_LAUNCH((k_restrict<T, N_, NT_, NB, 6>), dim3(n), dim3(256), lds, s, g, items));
+static void rview_nb(const DevGrid<T>& g, Wavelet w, const RItem* items, int n, int lds, int maxq,
+                     hipStream_t s) {
+  if (maxq <= 3)
+    MR_WAVELET_SWITCH(w, MR_LAUNCH((k_restrict<T, N_, NT_, NB, 3>), dim3(n), dim3(256), lds, s, g, items));
+  else
+    MR_WAVELET_SWITCH(w, MR_LAUNCH((k_restrict<T, N_, NT_, NB, 6>), dim3(n), dim3(256), lds, s, g, items));
 }
 template <typename T>
-static void rview_t(const void* dg, Wavelet w, const RItem* items, int n, int lds, hipStream_t s) {
+static void rview_t(const void* dg, Wavelet w, const RItem* items, int n, int lds, int maxq,
+                    hipStream_t s) {
   const DevGrid<T>& g = *static_cast<const DevGrid<T>*>(dg);
-  if (g.nb == 8) rview_nb<T, 8>(g, w, items, n, lds, s);
-  else if (g.nb == 16) rview_nb<T, 16>(g, w, items, n, lds, s);
-  else rview_nb<T, 24>(g, w, items, n, lds, s);
+  if (g.nb == 8) rview_nb<T, 8>(g, w, items, n, lds, maxq, s);
+  else if (g.nb == 16) rview_nb<T, 16>(g, w, items, n, lds, maxq, s);
+  else rview_nb<T, 24>(g, w, items, n, lds, maxq, s);
 }
-void launch_rview(bool f32, const void* dg, Wavelet w, const RItem* items, int n, int lds,
+void launch_rview(bool f32, const void* dg, Wavelet w, const RItem* items, int n, int lds, int maxq,
                   hipStream_t s) {
   if (n <= 0) return;
-  if (f32) rview_t<float>(dg, w, items, n, lds, s);
-  else rview_t<double>(dg, w, items, n, lds, s);
+  if (f32) rview_t<float>(dg, w, items, n, lds, maxq, s);
+  else rview_t<double>(dg, w, items, n, lds, maxq, s);
 }
 
 template <typename T, int FD, int NB>

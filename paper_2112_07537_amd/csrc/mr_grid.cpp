@@ -121,6 +121,7 @@ struct Lists {
   std::vector<GItem> g;
   std::vector<RItem> r;
   int lds_g = 0, lds_r = 0;
+  int maxq_r = 0;   // largest thinnest extent of the f->c items
   int64_t scratch_elems = 0;
   int64_t out_points = 0;
   DevBuf dg, dr;
@@ -574,7 +575,12 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
   L.lds_g = 0;
   for (const GItem& it : L.g) L.lds_g = std::max(L.lds_g, gview_lds(it, N, esz));
   L.lds_r = 0;
-  for (const RItem& it : L.r) L.lds_r = std::max(L.lds_r, rview_lds(it, H, esz));
+  L.maxq_r = 0;
+  for (const RItem& it : L.r) {
+    L.lds_r = std::max(L.lds_r, rview_lds(it, H, esz));
+    L.maxq_r = std::max(L.maxq_r, std::min(it.hi[0] - it.lo[0], std::min(it.hi[1] - it.lo[1], it.hi[2] - it.lo[2])));
+  }
+  if (L.maxq_r > 6) return fail(MR_EINVAL, "restriction item deeper than 6 coarse points");
   if (L.lds_g > 64 * 1024 || L.lds_r > 64 * 1024) return fail(MR_EINVAL, "ghost work item exceeds LDS");
   HIPCHK(L.dg.ensure(std::max<size_t>(1, L.g.size()) * sizeof(GItem)));
   HIPCHK(L.dr.ensure(std::max<size_t>(1, L.r.size()) * sizeof(RItem)));
@@ -716,9 +722,9 @@ static void ghost_fill(mr_grid* g, void* field, Lists& L) {
     prof_begin(g, 3, &a, &b, !plain);
     if (plain) {
       for (size_t i = 0; i < L.r.size(); ++i)
-        launch_rview(g->f32, v.raw, w, static_cast<const RItem*>(L.dr.p) + i, 1, L.lds_r, g->stream);
+        launch_rview(g->f32, v.raw, w, static_cast<const RItem*>(L.dr.p) + i, 1, L.lds_r, L.maxq_r, g->stream);
     } else {
-      launch_rview(g->f32, v.raw, w, static_cast<const RItem*>(L.dr.p), int(L.r.size()), L.lds_r, g->stream);
+      launch_rview(g->f32, v.raw, w, static_cast<const RItem*>(L.dr.p), int(L.r.size()), L.lds_r, L.maxq_r, g->stream);
     }
     prof_end(g, 3, a, b, !plain, L.out_points);
   }

@@ -104,7 +104,7 @@ struct Wavelet {
 void launch_gview(bool f32, const void* dg, Wavelet w, const GItem* items, int n_items,
                   int lds_bytes, hipStream_t s);
 void launch_rview(bool f32, const void* dg, Wavelet w, const RItem* items, int n_items,
-                  int lds_bytes, hipStream_t s);
+                  int lds, int maxq, hipStream_t s);
 // RK3 stage: out = a*un + b*(y + dt*rhs(y)); stage 0 ignores un.
 void launch_rhs(bool f32, const void* dg_y, const void* un, void* out, int fd_order, int depth,
                 double a_un, double b_y, double dt, const VelDev& vel, int first_blk,
