@@ -226,6 +226,16 @@ def main():
         log("cpu: %.4g points/s" % cpu["value"])
     g.close()
 
+    # -- the same steps with each RK3 step replayed as one captured hipGraph
+    if not args.no_plain:
+        log("fp32 hipGraph path")
+        gg = make_grid(cfg, exec_mode=2)
+        tg, pg, _, _ = timed_steps(gg, cfg, args.steps, args.warmup)
+        extra["graph_points_per_s"] = pg / tg
+        extra["graph_ms_per_step"] = 1e3 * tg / args.steps
+        log("hipGraph: %.3f ms/step" % extra["graph_ms_per_step"])
+        gg.close()
+
     # -- FP64 batched path (same kernels in FP64)
     if not args.no_plain:
         log("fp64 batched path")

@@ -959,16 +959,12 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
   __shared__ double t1[P * NB];     // after the x pass
   __shared__ double t2[NB * NB];    // after the y pass
   __shared__ Desc desc[27];
-  __shared__ unsigned long long bmax[27];
   __shared__ int nonfinite;
   // XCD-aware order: a block's halo is its Morton neighbours' data, which
   // then sits in the same XCD's L2
   const int b = first + xcd_item(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
-  if (tid < 27) {
-    make_desc(g, b, tid, desc[tid]);
-    bmax[tid] = 0ull;
-  }
+  if (tid < 27) make_desc(g, b, tid, desc[tid]);
   if (tid == 0) nonfinite = 0;
   __syncthreads();
   const int tx = tid % NB, ty = tid / NB;
@@ -1094,22 +1090,35 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
         det_out[(int64_t)slot * NB * NB * NB + ((int64_t)zo * NB + ty) * NB + tx] = isdet ? gsum : 0.0;
     }
   }
-  if (bad) atomicAdd(&nonfinite, 1);
-  // fold into the 27 boxes that contain this column
+  // Fold the column maxima into the 27 boxes (x-class, y-class, z-class;
+  // class 0 = [0, nb), 1 = [0, eb), 2 = [nb-ef, nb)) in two LDS stages:
+  // per row and x-class, then per box over the rows of its y-class.
+  // (No LDS atomics: a contended atomic max is expanded into a per-lane
+  // loop.)  The buffers of the plane loop are free by now.
+  double* colmax = pl;                 // [ty][tx] for one z-class
+  double* rowmax = t1;                 // [cz][ty][cx]
+  static_assert(P * P >= NB * NB && P * NB >= NB * 9, "reduction buffers");
+  if (bad) nonfinite = 1;
   const double mz[3] = {m0, m1, m2};
-  const bool inx[3] = {true, tx < eb, tx >= NB - ef};
-  const bool iny[3] = {true, ty < eb, ty >= NB - ef};
 #pragma unroll
-  for (int cz = 0; cz < 3; ++cz)
-#pragma unroll
-    for (int cy = 0; cy < 3; ++cy)
-#pragma unroll
-      for (int cx = 0; cx < 3; ++cx)
-        if (inx[cx] && iny[cy])
-          atomicMax(&bmax[cx + 3 * cy + 9 * cz], (unsigned long long)__double_as_longlong(mz[cz]));
+  for (int cz = 0; cz < 3; ++cz) {
+    __syncthreads();
+    colmax[ty * NB + tx] = mz[cz];
+    __syncthreads();
+    if (tid < NB * 3) {
+      const int y = tid / 3, cx = tid % 3;
+      const int x0 = cx == 2 ? NB - ef : 0, x1 = cx == 1 ? eb : NB;
+      double v = 0.0;
+      for (int x = x0; x < x1; ++x) v = fmax(v, colmax[y * NB + x]);
+      rowmax[(cz * NB + y) * 3 + cx] = v;
+    }
+  }
   __syncthreads();
   if (tid < 27) {
-    double v = __longlong_as_double((long long)bmax[tid]);
+    const int cx = tid % 3, cy = (tid / 3) % 3, cz = tid / 9;
+    const int y0 = cy == 2 ? NB - ef : 0, y1 = cy == 1 ? eb : NB;
+    double v = 0.0;
+    for (int y = y0; y < y1; ++y) v = fmax(v, rowmax[(cz * NB + y) * 3 + cx]);
     if (nonfinite) v = __longlong_as_double(0x7ff8000000000000ll);
     bands[(int64_t)b * 27 + tid] = v;
   }
