@@ -436,7 +436,7 @@ __global__ __launch_bounds__(256) void k_gview(DevGrid<T> g, const GItem* __rest
   T* T2 = S;
   __syncthreads();
   {
-    constexpr int U = 4;
+    constexpr int U = 16;   // one round of loads covers a side item's samples
     const int n = cs[0] * cs[1] * cs[2];
     Iter3 q(tid, nt, cs[0], cs[1]);
     for (int i0 = tid; i0 < n; i0 += U * nt) {
@@ -627,10 +627,10 @@ __global__ __launch_bounds__(256) void k_restrict(DevGrid<T> g, const RItem* __r
     xs[a] = 2 * (qs[a] - 1) + 1 + 2 * H;
   }
   // reduction order: n (thinnest), then a1, then a2
-  int n = 0;
-  if (qs[1] < qs[n]) n = 1;
-  if (qs[2] < qs[n]) n = 2;
-  const int a1 = n == 0 ? 1 : 0, a2 = n == 2 ? 1 : 2;
+  // pass 1 runs along y or z (the thinner of the two), so that the lanes of
+  // a wave, which walk along x, read consecutive addresses
+  const int n = qs[1] <= qs[2] ? 1 : 2;
+  const int a1 = 0, a2 = n == 2 ? 1 : 2;
   T* R1 = lds;                               // [xs_a2][xs_a1][qs_n]
   T* R2 = R1 + qs[n] * xs[a1] * xs[a2];      // [xs_a2][qs_a1][qs_n]
   const int ox = g.ijk[3 * F] * NB, oy = g.ijk[3 * F + 1] * NB, oz = g.ijk[3 * F + 2] * NB;
@@ -1384,15 +1384,17 @@ void launch_gview(bool f32, const void* dg, Wavelet w, const GItem* items, int n
   else gview_t<double>(dg, w, items, n, lds, s);
 }
 
-// MAXQ bounds the coarse points per column of pass 1 (the item's thinnest
-// extent): 3 covers stencil-depth fills up to FD6, 6 the widest fills.
+// MAXQ bounds the coarse points per column of pass 1 (the item's extent
+// along y or z, whichever is thinner): 3, 6 or 12.
 template <typename T, int NB>
 static void rview_nb(const DevGrid<T>& g, Wavelet w, const RItem* items, int n, int lds, int maxq,
                      hipStream_t s) {
   if (maxq <= 3)
     MR_WAVELET_SWITCH(w, MR_LAUNCH((k_restrict<T, N_, NT_, NB, 3>), dim3(n), dim3(256), lds, s, g, items));
-  else
+  else if (maxq <= 6)
     MR_WAVELET_SWITCH(w, MR_LAUNCH((k_restrict<T, N_, NT_, NB, 6>), dim3(n), dim3(256), lds, s, g, items));
+  else
+    MR_WAVELET_SWITCH(w, MR_LAUNCH((k_restrict<T, N_, NT_, NB, 12>), dim3(n), dim3(256), lds, s, g, items));
 }
 template <typename T>
 static void rview_t(const void* dg, Wavelet w, const RItem* items, int n, int lds, int maxq,

@@ -120,8 +120,11 @@ struct DevBuf {
 struct Lists {
   std::vector<GItem> g;
   std::vector<RItem> r;
-  int lds_g = 0, lds_r = 0;
-  int maxq_r = 0;   // largest thinnest extent of the f->c items
+  int lds_g = 0;
+  // f->c items grouped by pass-1 column length (extent along y or z):
+  // classes <= 3, <= 6, <= 12 at [rcls[c], rcls[c+1]) with their LDS sizes
+  int rcls[4] = {0, 0, 0, 0};
+  int lds_rc[3] = {0, 0, 0};
   int64_t scratch_elems = 0;
   int64_t out_points = 0;
   DevBuf dg, dr;
@@ -371,10 +374,8 @@ static int rview_lds(const RItem& it, int H, size_t esz) {
     qs[a] = it.hi[a] - it.lo[a];
     xs[a] = 2 * (qs[a] - 1) + 1 + 2 * H;
   }
-  int n = 0;
-  if (qs[1] < qs[n]) n = 1;
-  if (qs[2] < qs[n]) n = 2;
-  const int a1 = n == 0 ? 1 : 0, a2 = n == 2 ? 1 : 2;
+  const int n = qs[1] <= qs[2] ? 1 : 2;   // pass 1 never runs along x
+  const int a1 = 0, a2 = n == 2 ? 1 : 2;
   return int(esz * (size_t(qs[n]) * xs[a1] * xs[a2] + size_t(qs[n]) * qs[a1] * xs[a2]));
 }
 
@@ -574,14 +575,28 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
   }
   L.lds_g = 0;
   for (const GItem& it : L.g) L.lds_g = std::max(L.lds_g, gview_lds(it, N, esz));
-  L.lds_r = 0;
-  L.maxq_r = 0;
-  for (const RItem& it : L.r) {
-    L.lds_r = std::max(L.lds_r, rview_lds(it, H, esz));
-    L.maxq_r = std::max(L.maxq_r, std::min(it.hi[0] - it.lo[0], std::min(it.hi[1] - it.lo[1], it.hi[2] - it.lo[2])));
+  {
+    auto cls = [](const RItem& it) {
+      const int q = std::min(it.hi[1] - it.lo[1], it.hi[2] - it.lo[2]);
+      return q <= 3 ? 0 : (q <= 6 ? 1 : (q <= 12 ? 2 : 3));
+    };
+    std::vector<RItem> sorted;
+    sorted.reserve(L.r.size());
+    for (int c = 0; c < 3; ++c) {
+      L.rcls[c] = int(sorted.size());
+      L.lds_rc[c] = 0;
+      for (const RItem& it : L.r)
+        if (cls(it) == c) {
+          sorted.push_back(it);
+          L.lds_rc[c] = std::max(L.lds_rc[c], rview_lds(it, H, esz));
+        }
+    }
+    L.rcls[3] = int(sorted.size());
+    if (sorted.size() != L.r.size()) return fail(MR_EINVAL, "restriction item wider than 12 coarse points");
+    L.r.swap(sorted);
   }
-  if (L.maxq_r > 6) return fail(MR_EINVAL, "restriction item deeper than 6 coarse points");
-  if (L.lds_g > 64 * 1024 || L.lds_r > 64 * 1024) return fail(MR_EINVAL, "ghost work item exceeds LDS");
+  const int lds_r = std::max(L.lds_rc[0], std::max(L.lds_rc[1], L.lds_rc[2]));
+  if (L.lds_g > 64 * 1024 || lds_r > 64 * 1024) return fail(MR_EINVAL, "ghost work item exceeds LDS");
   HIPCHK(L.dg.ensure(std::max<size_t>(1, L.g.size()) * sizeof(GItem)));
   HIPCHK(L.dr.ensure(std::max<size_t>(1, L.r.size()) * sizeof(RItem)));
   if (!L.g.empty())
@@ -718,13 +733,18 @@ static void ghost_fill(mr_grid* g, void* field, Lists& L) {
     }
     prof_end(g, 2, a, b, !plain, L.out_points);
   }
-  if (!L.r.empty()) {
+  // one launch per column-length class (the classes are independent)
+  static const int kMaxq[3] = {3, 6, 12};
+  const RItem* ritems = static_cast<const RItem*>(L.dr.p);
+  for (int c = 0; c < 3; ++c) {
+    const int i0 = L.rcls[c], i1 = L.rcls[c + 1];
+    if (i1 <= i0) continue;
     prof_begin(g, 3, &a, &b, !plain);
     if (plain) {
-      for (size_t i = 0; i < L.r.size(); ++i)
-        launch_rview(g->f32, v.raw, w, static_cast<const RItem*>(L.dr.p) + i, 1, L.lds_r, L.maxq_r, g->stream);
+      for (int i = i0; i < i1; ++i)
+        launch_rview(g->f32, v.raw, w, ritems + i, 1, L.lds_rc[c], kMaxq[c], g->stream);
     } else {
-      launch_rview(g->f32, v.raw, w, static_cast<const RItem*>(L.dr.p), int(L.r.size()), L.lds_r, L.maxq_r, g->stream);
+      launch_rview(g->f32, v.raw, w, ritems + i0, i1 - i0, L.lds_rc[c], kMaxq[c], g->stream);
     }
     prof_end(g, 3, a, b, !plain, L.out_points);
   }
@@ -1583,7 +1603,7 @@ mr_status mr_tree_stats(const mr_grid* g, int64_t out[10]) {
   out[5] = int64_t(g->stage.g.size());
   out[6] = int64_t(g->stage.r.size());
   out[7] = g->stage.lds_g;
-  out[8] = g->stage.lds_r;
+  out[8] = std::max(g->stage.lds_rc[0], std::max(g->stage.lds_rc[1], g->stage.lds_rc[2]));
   out[9] = g->patch_elems;
   return MR_OK;
 }
