@@ -473,73 +473,105 @@ __global__ __launch_bounds__(256) void k_gview(DevGrid<T> g, const GItem* __rest
     }
   }
   __syncthreads();
-  {  // y: pairs along y, columns (x, z)
-    const int n = fs[0] * np[1] * cs[2];
-    Iter3 q(tid, nt, fs[0], np[1]);
-    for (int i = tid; i < n; i += nt, q.advance()) {
-      const T* src = T1 + (q.z * cs[1] + q.y) * fs[0] + q.x;
-      T od = T(0);
+  // y and z passes by line segments: a work unit refines K consecutive
+  // pairs of one line from a register window of N + K - 1 samples (line
+  // index fastest across threads, so neighbouring lanes read neighbouring
+  // LDS words)
+  constexpr int K = 4;
+  auto segment = [&](const T* src, int ss, int j0, int jn, auto&& put) {
+    T win[N + K - 1];
 #pragma unroll
-      for (int k = 0; k < N; ++k) od += T(DD<N>::w(k)) * src[k * fs[0]];
-      const int y0 = 2 * q.y - e[1];
-      T* dst = T2 + q.z * fs[1] * fs[0] + q.x;
-      if (y0 >= 0) dst[y0 * fs[0]] = src[HN * fs[0]];
-      if (y0 + 1 < fs[1]) dst[(y0 + 1) * fs[0]] = od;
+    for (int k = 0; k < N + K - 1; ++k) win[k] = k < N - 1 + jn ? src[(j0 + k) * ss] : T(0);
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      if (q < jn) {
+        T od = T(0);
+#pragma unroll
+        for (int k = 0; k < N; ++k) od += T(DD<N>::w(k)) * win[q + k];
+        put(j0 + q, win[q + HN], od);
+      }
+    }
+  };
+  {  // y: lines (x, z) of T1, pairs along y
+    const int nl = fs[0] * cs[2], nseg = (np[1] + K - 1) / K;
+    int l = tid, sg = 0;
+    while (l >= nl) { l -= nl; ++sg; }
+    for (int u = tid; u < nl * nseg; u += nt) {
+      const int qx = l % fs[0], qz = l / fs[0];
+      const T* src = T1 + qz * cs[1] * fs[0] + qx;
+      T* dst = T2 + qz * fs[1] * fs[0] + qx;
+      const int j0 = sg * K, jn = min(K, np[1] - j0);
+      segment(src, fs[0], j0, jn, [&](int j, T ev, T od) {
+        const int y0 = 2 * j - e[1];
+        if (y0 >= 0) dst[y0 * fs[0]] = ev;
+        if (y0 + 1 < fs[1]) dst[(y0 + 1) * fs[0]] = od;
+      });
+      l += nt;
+      while (l >= nl) { l -= nl; ++sg; }
     }
   }
   __syncthreads();
   constexpr int64_t nb3 = (int64_t)NB * NB * NB;
   const bool slab = (it.sel & 16) != 0;
-  {  // z: pairs along z, written out
-    const int n = fs[0] * fs[1] * np[2];
+  {  // z: lines (x, y) of T2, pairs along z, written out
+    const int nl = fs[0] * fs[1], nseg = (np[2] + K - 1) / K;
     const int plane = fs[0] * fs[1];
-    Iter3 q(tid, nt, fs[0], fs[1]);
-    for (int i = tid; i < n; i += nt, q.advance()) {
-      const T* src = T2 + (q.z * fs[1] + q.y) * fs[0] + q.x;
-      T od = T(0);
+    const int dw = g.dw;
+    int l = tid, sg = 0;
+    while (l >= nl) { l -= nl; ++sg; }
+    for (int u = tid; u < nl * nseg; u += nt) {
+      const int qx = l % fs[0], qy = l / fs[0];
+      const int x = it.lo[0] + qx, y = it.lo[1] + qy;
+      const T* src = T2 + l;
+      const int j0 = sg * K, jn = min(K, np[2] - j0);
+      if (slab) {
+        // selector of section 2.2.4 for the two parities of z (the pair
+        // starts on an even z)
+        bool take[2];
 #pragma unroll
-      for (int k = 0; k < N; ++k) od += T(DD<N>::w(k)) * src[k * plane];
-      const T ev = src[HN * plane];
-      const int x = it.lo[0] + q.x, y = it.lo[1] + q.y;
-      const int z0 = it.lo[2] + 2 * q.z - e[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int z = z0 + h;
-        if (z < it.lo[2] || z >= it.hi[2]) continue;
-        const T v = h ? od : ev;
-        if (slab) {
-          const int par[3] = {x & 1, y & 1, z & 1};
-          bool take;
+        for (int h = 0; h < 2; ++h) {
+          const int par[3] = {x & 1, y & 1, h};
           if (it.sel & 8) {
-            take = (par[0] | par[1] | par[2]) != 0;
+            take[h] = (par[0] | par[1] | par[2]) != 0;
           } else {
-            take = true;
-            bool tang_odd = false;
+            bool t = true, tang_odd = false;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-              if (it.sel & (1 << a)) take = take && (par[a] == 0);
+              if (it.sel & (1 << a)) t = t && (par[a] == 0);
               else tang_odd = tang_odd || (par[a] == 1);
             }
-            take = take && tang_odd;
-          }
-          if (take) g.field[m * nb3 + (z * NB + y) * NB + x] = v;
-        } else {
-          // region of the point and its place in that region's patch box
-          // (depth dw on the axes outside the block)
-          const int rx = x < 0 ? 0 : (x < NB ? 1 : 2);
-          const int ry = y < 0 ? 0 : (y < NB ? 1 : 2);
-          const int rz = z < 0 ? 0 : (z < NB ? 1 : 2);
-          const int r = rx + 3 * ry + 9 * rz;
-          if ((it.rmask >> r) & 1) {
-            const int dw = g.dw;
-            const int sx = rx == 1 ? NB : dw, sy = ry == 1 ? NB : dw;
-            const int lx = x + (rx == 0 ? dw : (rx == 1 ? 0 : -NB));
-            const int ly = y + (ry == 0 ? dw : (ry == 1 ? 0 : -NB));
-            const int lz = z + (rz == 0 ? dw : (rz == 1 ? 0 : -NB));
-            g.patch[roff[r] + (lz * sy + ly) * sx + lx] = v;
+            take[h] = t && tang_odd;
           }
         }
+        T* col = g.field + m * nb3 + y * NB + x;
+        segment(src, plane, j0, jn, [&](int j, T ev, T od) {
+          const int z0 = it.lo[2] + 2 * j - e[2];
+          if (take[0] && z0 >= it.lo[2]) col[z0 * (NB * NB)] = ev;
+          if (take[1] && z0 + 1 < it.hi[2]) col[(z0 + 1) * (NB * NB)] = od;
+        });
+      } else {
+        // region of the column and its place in that region's patch box
+        // (depth dw on the axes outside the block); a pair never straddles
+        // a region boundary in z (both are even)
+        const int rx = x < 0 ? 0 : (x < NB ? 1 : 2);
+        const int ry = y < 0 ? 0 : (y < NB ? 1 : 2);
+        const int sx = rx == 1 ? NB : dw, sy = ry == 1 ? NB : dw;
+        const int lxy = (y + (ry == 0 ? dw : (ry == 1 ? 0 : -NB))) * sx +
+                        x + (rx == 0 ? dw : (rx == 1 ? 0 : -NB));
+        segment(src, plane, j0, jn, [&](int j, T ev, T od) {
+          const int z0 = it.lo[2] + 2 * j - e[2];
+          const int rz = z0 < 0 ? 0 : (z0 < NB ? 1 : 2);
+          const int r = rx + 3 * ry + 9 * rz;
+          if ((it.rmask >> r) & 1) {
+            const int lz = z0 + (rz == 0 ? dw : (rz == 1 ? 0 : -NB));
+            T* dst = g.patch + roff[r] + lz * (sx * sy) + lxy;
+            if (z0 >= it.lo[2]) dst[0] = ev;
+            if (z0 + 1 < it.hi[2]) dst[sx * sy] = od;
+          }
+        });
       }
+      l += nt;
+      while (l >= nl) { l -= nl; ++sg; }
     }
   }
 }

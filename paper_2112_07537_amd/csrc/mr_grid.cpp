@@ -164,6 +164,7 @@ struct mr_grid {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   HostTimer htime;
+  DevBuf ad_pairs, ad_items, ad_scr, ad_det, ad_slot;   // adaptation scratch
   bool f32 = false;
   int nb = 16, N = 4, Nt = 0, G = 2, Dw = 4;
   int Ef = 0, Eb = 0;
@@ -1053,7 +1054,12 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
         }
       }
     }
-    DevBuf d_pairs, d_items, d_scr, d_det, d_slot;
+    // grow-only buffers kept by the grid (no allocation per adaptation)
+    DevBuf& d_pairs = g->ad_pairs;
+    DevBuf& d_items = g->ad_items;
+    DevBuf& d_scr = g->ad_scr;
+    DevBuf& d_det = g->ad_det;
+    DevBuf& d_slot = g->ad_slot;
     HIPCHK(d_scr.ensure(std::max<int64_t>(1, scr) * sizeof(double)));
     HIPCHK(d_det.ensure(std::max<int64_t>(1, int64_t(nslot) * nb * nb * nb) * sizeof(double)));
     HIPCHK(d_slot.ensure(std::max(1, n_old) * sizeof(int32_t)));
@@ -1102,11 +1108,6 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
     }
     mr_status st = check_err(g);
     HIPCHK(hipStreamSynchronize(g->stream));
-    d_pairs.release();
-    d_items.release();
-    d_scr.release();
-    d_det.release();
-    d_slot.release();
     if (st != MR_OK) return st;
     for (int f = 0; f < g->cfg.n_fields; ++f) std::swap(g->fields[f], g->alts[f]);
   }
@@ -1309,7 +1310,8 @@ mr_status mr_grid_destroy(mr_grid* g) {
   for (auto& b : g->alts) b.release();
   DevBuf* bufs[] = {&g->tmpA, &g->tmpB, &g->d_lev, &g->d_ijk, &g->d_cmap, &g->d_poff, &g->d_patch,
                     &g->d_scratch, &g->d_err, &g->d_bands, &g->d_norms, &g->d_icpar, &g->d_mom,
-                    &g->stage.dg, &g->stage.dr, &g->wide.dg, &g->wide.dr};
+                    &g->stage.dg, &g->stage.dr, &g->wide.dg, &g->wide.dr, &g->ad_pairs,
+                    &g->ad_items, &g->ad_scr, &g->ad_det, &g->ad_slot};
   for (DevBuf* b : bufs) b->release();
   if (g->own_stream) (void)hipStreamDestroy(g->stream);
   delete g;
