@@ -707,14 +707,19 @@ __global__ __launch_bounds__(256) void k_restrict(DevGrid<T> g, const RItem* __r
                                                         : pn0 + xs[n] > NB);
         inj = inj || (used && d.patch == 2);
       }
-      const int j0 = -pn0, j1 = NB - pn0;   // region boundaries along the column
+      // region boundaries along the column: the column start is the item's
+      // xlo[n] for every lane, so the segment of each load is uniform
+      const int xs_n = __builtin_amdgcn_readfirstlane(xs[n]);
+      const int j0 = __builtin_amdgcn_readfirstlane(-xlo[n]);
+      const int j1 = __builtin_amdgcn_readfirstlane(NB - xlo[n]);
       T col[XS];
       if (!inj) {
 #pragma unroll
         for (int j = 0; j < XS; ++j) {
-          const int jj = j < xs[n] ? j : xs[n] - 1;
-          const int rn = jj < j0 ? 0 : (jj < j1 ? 1 : 2);
-          col[j] = sp[rn][jj * sst[rn]];
+          const int jj = j < xs_n ? j : xs_n - 1;
+          if (jj < j0) col[j] = sp[0][jj * sst[0]];
+          else if (jj < j1) col[j] = sp[1][jj * sst[1]];
+          else col[j] = sp[2][jj * sst[2]];
         }
       } else {
         // a finer-still leaf inside the window: resolve every point
