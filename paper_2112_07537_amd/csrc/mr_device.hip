@@ -362,39 +362,41 @@ __device__ __forceinline__ int xcd_item(int i, int n) {
   return x * q + (x < r ? x : r) + k;
 }
 
-// Affine address table of the 64 owner-map cells of block m for coarse
-// samples: the level-(L-1) sample c (relative to m's origin, i.e. the
-// level-L point p = 2c) held by the leaf of cell k sits at element
+// Affine address table of the 64 owner-map cells of a block for coarse
+// samples: the level-(L-1) sample c (relative to the block's origin, i.e.
+// the level-L point p = 2c) held by the leaf of cell k sits at element
 //   base[k] + step[k] * (c_x + NB c_y + NB^2 c_z)
 // of the field (step 1, 2 or 4 for a leaf one level coarser, at the same
 // level, one level finer).  The periodic wrap is constant inside a cell,
-// so it is folded into base.  Sets *bad for a leaf outside L-1..L+1.
+// so it is folded into base.  The table depends on the tree only; it is
+// built once per tree, one thread per (block, cell), and flags leaves
+// outside L-1..L+1.
 template <typename T, int NB>
-__device__ __forceinline__ void sample_table(const DevGrid<T>& g, int m, int L, int64_t* base,
-                                             int32_t* step, int* bad) {
-  const int t = threadIdx.x;
-  if (t < 64) {
-    constexpr int H = NB / 2;
-    const int id = g.cmap[m * 64 + t];
-    const int l = g.lev[id];
-    const int W = NB << L;
-    const int cc[3] = {t & 3, (t >> 2) & 3, t >> 4};
-    int64_t b = (int64_t)id * (NB * NB * NB);
-    int64_t mul = 1;
+__global__ void k_cell_tables(DevGrid<T> g, int64_t* base, int32_t* step, int n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * 64) return;
+  const int m = int(i >> 6), t = int(i & 63);
+  constexpr int H = NB / 2;
+  const int L = g.lev[m];
+  const int id = g.cmap[i];
+  const int l = g.lev[id];
+  const int W = NB << L;
+  const int cc[3] = {t & 3, (t >> 2) & 3, t >> 4};
+  int64_t b = (int64_t)id * (NB * NB * NB);
+  int64_t mul = 1;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int O = g.ijk[3 * m + a] * NB;
-      const int X0 = O + (cc[a] - 1) * H;
-      const int shift = X0 - wrap1(X0, W);
-      const int o = g.ijk[3 * id + a] * NB;
-      const int base_a = l == L ? (O - shift) - o : (l > L ? 2 * (O - shift) - o : (O - shift) / 2 - o);
-      b += mul * base_a;
-      mul *= NB;
-    }
-    base[t] = b;
-    step[t] = l == L ? 2 : (l > L ? 4 : 1);
-    if (l < L - 1 || l > L + 1) atomicAdd(bad, 1);
+  for (int a = 0; a < 3; ++a) {
+    const int O = g.ijk[3 * m + a] * NB;
+    const int X0 = O + (cc[a] - 1) * H;
+    const int shift = X0 - wrap1(X0, W);
+    const int o = g.ijk[3 * id + a] * NB;
+    const int base_a = l == L ? (O - shift) - o : (l > L ? 2 * (O - shift) - o : (O - shift) / 2 - o);
+    b += mul * base_a;
+    mul *= NB;
   }
+  base[i] = b;
+  step[i] = l == L ? 2 : (l > L ? 4 : 1);
+  if (l < L - 1 || l > L + 1) atomicAdd(g.err, 1);
 }
 
 // One workgroup per GItem.  S = coarse samples [cs2][cs1][cs0], T1 = refined
@@ -425,7 +427,10 @@ __global__ __launch_bounds__(256) void k_gview(DevGrid<T> g, const GItem* __rest
     np[a] = p1 - p0 + 1;
     e[a] = it.lo[a] & 1;   // 1: the first pair's even point is outside the box
   }
-  sample_table<T, NB>(g, m, L, cbase, cstep, g.err);
+  if (tid < 64) {
+    cbase[tid] = g.cbase[(int64_t)m * 64 + tid];
+    cstep[tid] = g.cstep[(int64_t)m * 64 + tid];
+  }
   if (tid >= 128 && tid < 128 + 27) roff[tid - 128] = g.poff[(int64_t)m * 27 + tid - 128];
   if (tid < 96) {
     const int a = tid >> 5, i = tid & 31;
@@ -1419,6 +1424,27 @@ void launch_gview(bool f32, const void* dg, Wavelet w, const GItem* items, int n
   if (n <= 0) return;
   if (f32) gview_t<float>(dg, w, items, n, lds, s);
   else gview_t<double>(dg, w, items, n, lds, s);
+}
+
+template <typename T, int NB>
+static void ctab_nb(const DevGrid<T>& g, int n, hipStream_t s) {
+  const int64_t th = (int64_t)n * 64;
+  MR_LAUNCH((k_cell_tables<T, NB>), dim3(unsigned((th + 255) / 256)), dim3(256), 0, s, g,
+            const_cast<int64_t*>(g.cbase), const_cast<int32_t*>(g.cstep), n);
+}
+void launch_cell_tables(bool f32, const void* dg, int n, hipStream_t s) {
+  if (n <= 0) return;
+  if (f32) {
+    const DevGrid<float>& g = *static_cast<const DevGrid<float>*>(dg);
+    if (g.nb == 8) ctab_nb<float, 8>(g, n, s);
+    else if (g.nb == 16) ctab_nb<float, 16>(g, n, s);
+    else ctab_nb<float, 24>(g, n, s);
+  } else {
+    const DevGrid<double>& g = *static_cast<const DevGrid<double>*>(dg);
+    if (g.nb == 8) ctab_nb<double, 8>(g, n, s);
+    else if (g.nb == 16) ctab_nb<double, 16>(g, n, s);
+    else ctab_nb<double, 24>(g, n, s);
+  }
 }
 
 // MAXQ bounds the coarse points per column of pass 1 (the item's extent

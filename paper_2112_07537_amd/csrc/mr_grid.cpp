@@ -178,7 +178,7 @@ struct mr_grid {
   // device
   std::vector<DevBuf> fields, alts;
   DevBuf tmpA, tmpB;
-  DevBuf d_lev, d_ijk, d_cmap, d_poff, d_patch, d_scratch, d_err;
+  DevBuf d_lev, d_ijk, d_cmap, d_poff, d_patch, d_scratch, d_err, d_cbase, d_cstep;
   DevBuf d_bands, d_norms, d_icpar, d_mom;
   Lists stage, wide;
   Prof prof;
@@ -609,6 +609,7 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
 
 // Upload tree metadata and rebuild every derived structure.
 static mr_status commit_tree_impl(mr_grid* g);
+static void build_cell_tables(mr_grid* g);
 static mr_status commit_tree(mr_grid* g) {
   const double t0 = now_ms();
   mr_status st = commit_tree_impl(g);
@@ -654,6 +655,9 @@ static mr_status commit_tree_impl(mr_grid* g) {
     HIPCHK(hipMemcpyAsync(g->d_ijk.p, ijk.data(), 3 * n * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
     HIPCHK(hipMemcpyAsync(g->d_cmap.p, g->cmap.data(), 64 * size_t(n) * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
     HIPCHK(hipMemcpyAsync(g->d_poff.p, g->poff.data(), 27 * size_t(n) * sizeof(int64_t), hipMemcpyHostToDevice, g->stream));
+    HIPCHK(g->d_cbase.ensure(64 * size_t(n) * sizeof(int64_t)));
+    HIPCHK(g->d_cstep.ensure(64 * size_t(n) * sizeof(int32_t)));
+    build_cell_tables(g);
   }
   st = build_lists(g, g->G, g->stage);
   if (st != MR_OK) return st;
@@ -675,6 +679,8 @@ static DevGrid<T> view(mr_grid* g, void* field) {
   d.ijk = static_cast<const int32_t*>(g->d_ijk.p);
   d.cmap = static_cast<const int32_t*>(g->d_cmap.p);
   d.poff = static_cast<const int64_t*>(g->d_poff.p);
+  d.cbase = static_cast<const int64_t*>(g->d_cbase.p);
+  d.cstep = static_cast<const int32_t*>(g->d_cstep.p);
   d.field = static_cast<T*>(field);
   d.patch = static_cast<T*>(g->d_patch.p);
   d.scratch = static_cast<T*>(g->d_scratch.p);
@@ -696,6 +702,12 @@ static AnyView anyview(mr_grid* g, void* field) {
     std::memcpy(v.raw, &d, sizeof(d));
   }
   return v;
+}
+
+// Per-block coarse-sample address tables (depend on the tree only).
+static void build_cell_tables(mr_grid* g) {
+  AnyView v = anyview(g, nullptr);
+  launch_cell_tables(g->f32, v.raw, int(g->leaves.size()), g->stream);
 }
 
 // Kernel timers: events stamped by the runtime at the start and end of the
@@ -1311,6 +1323,7 @@ mr_status mr_grid_destroy(mr_grid* g) {
   DevBuf* bufs[] = {&g->tmpA, &g->tmpB, &g->d_lev, &g->d_ijk, &g->d_cmap, &g->d_poff, &g->d_patch,
                     &g->d_scratch, &g->d_err, &g->d_bands, &g->d_norms, &g->d_icpar, &g->d_mom,
                     &g->stage.dg, &g->stage.dr, &g->wide.dg, &g->wide.dr, &g->ad_pairs,
+                    &g->d_cbase, &g->d_cstep,
                     &g->ad_items, &g->ad_scr, &g->ad_det, &g->ad_slot};
   for (DevBuf* b : bufs) b->release();
   if (g->own_stream) (void)hipStreamDestroy(g->stream);

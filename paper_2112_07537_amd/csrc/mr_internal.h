@@ -77,6 +77,8 @@ struct DevGrid {
   const int32_t* cmap;   // [64*nblk] leaf id per half-block cell of the
                          //   4x4x4 cells covering [-nb/2, 3nb/2)^3
   const int64_t* poff;   // [27*nblk] patch offset per region, -1 if none
+  const int64_t* cbase;  // [64*nblk] coarse-sample address table per cell
+  const int32_t* cstep;  //   (see k_cell_tables)
   T* field;              // [nblk * nb^3]
   T* patch;
   T* scratch;
@@ -103,6 +105,7 @@ struct Wavelet {
 
 void launch_gview(bool f32, const void* dg, Wavelet w, const GItem* items, int n_items,
                   int lds_bytes, hipStream_t s);
+void launch_cell_tables(bool f32, const void* dg, int n_blocks, hipStream_t s);
 void launch_rview(bool f32, const void* dg, Wavelet w, const RItem* items, int n_items,
                   int lds, int maxq, hipStream_t s);
 // RK3 stage: out = a*un + b*(y + dt*rhs(y)); stage 0 ignores un.
