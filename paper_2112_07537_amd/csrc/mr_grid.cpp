@@ -380,11 +380,17 @@ static int rview_lds(const RItem& it, int H, size_t esz) {
   return int(esz * (size_t(qs[n]) * xs[a1] * xs[a2] + size_t(qs[n]) * qs[a1] * xs[a2]));
 }
 
-static const int kLdsBudget = 48 * 1024;
+// LDS per work item is bounded by tiling: every workgroup of a launch
+// reserves the largest item's LDS, so smaller tiles raise the number of
+// resident workgroups.  The budgets were chosen by timing the c->f and f->c
+// launches on MI355X (20 KB and 24 KB beat 16, 32 and 48 KB); the c->f
+// values do not depend on the tiling, and the f->c tiling is fixed.
+static const int kLdsBudgetRefine = 20 * 1024;
+static const int kLdsBudgetRestrict = 24 * 1024;
 
 // Split a box along its longest axis until the LDS estimate fits the budget.
 template <typename Item, typename F>
-static void push_tiled(std::vector<Item>& out, Item it, F lds_of) {
+static void push_tiled(std::vector<Item>& out, Item it, F lds_of, int kLdsBudget) {
   std::vector<Item> todo{it};
   while (!todo.empty()) {
     Item c = todo.back();
@@ -479,7 +485,7 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
           for (int a = 0; a < 3; ++a, mul *= 3) r2 += mul * ((sub >> a) & 1 ? rr[a] : 1);
           if (region_level(g, b, r2) < Lb) covered = true;
         }
-        if (!sempty && !covered) push_tiled(P.g, sb, glds);
+        if (!sempty && !covered) push_tiled(P.g, sb, glds, kLdsBudgetRefine);
       } else {
         // f->c: each finer leaf covering this region restricts its part
         region_box(nb, D, r, blo, bhi);
@@ -510,7 +516,7 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
               if (g->leaves[it.fblk].L != Lb + 1)
                 return false;
               P.pts += box_size(it.lo, it.hi);
-              push_tiled(P.r, it, rlds);
+              push_tiled(P.r, it, rlds, kLdsBudgetRestrict);
             }
       }
     }
@@ -545,7 +551,7 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
           pt.lo[c] = lo[c];
           pt.hi[c] = hi[c];
         }
-        push_tiled(P.g, pt, glds);
+        push_tiled(P.g, pt, glds, kLdsBudgetRefine);
       }
       return true;
   };
