@@ -148,38 +148,6 @@ __device__ __forceinline__ int owner_id(const DevGrid<T>& g, int m, int up, int 
   return g.cmap[m * 64 + (cz * 4 + cy) * 4 + cx];
 }
 
-// Value of leaf `id` at the level-Lq point with global coordinates Q (wrapped
-// here); requires Q on the leaf's grid.  Returns false if it is not.
-template <typename T>
-__device__ __forceinline__ bool leaf_value(const DevGrid<T>& g, int id, int Lq, int Qx, int Qy,
-                                           int Qz, T& v) {
-  const int nb = g.nb;
-  const int W = nb << Lq;
-  Qx = wrapi(Qx, W);
-  Qy = wrapi(Qy, W);
-  Qz = wrapi(Qz, W);
-  const int l = g.lev[id];
-  int lx, ly, lz;
-  if (l >= Lq) {
-    int s = l - Lq;
-    lx = (Qx << s) - g.ijk[3 * id] * nb;
-    ly = (Qy << s) - g.ijk[3 * id + 1] * nb;
-    lz = (Qz << s) - g.ijk[3 * id + 2] * nb;
-  } else {
-    int s = Lq - l, msk = (1 << s) - 1;
-    if ((Qx & msk) | (Qy & msk) | (Qz & msk)) return false;
-    lx = (Qx >> s) - g.ijk[3 * id] * nb;
-    ly = (Qy >> s) - g.ijk[3 * id + 1] * nb;
-    lz = (Qz >> s) - g.ijk[3 * id + 2] * nb;
-  }
-  if ((unsigned)lx >= (unsigned)nb || (unsigned)ly >= (unsigned)nb || (unsigned)lz >= (unsigned)nb) {
-    atomicAdd(g.err, 1);
-    return false;
-  }
-  v = g.field[(int64_t)id * nb * nb * nb + ((int64_t)lz * nb + ly) * nb + lx];
-  return true;
-}
-
 // Value of block b's level-L field extended by its ghost layer: own points,
 // same-level neighbours, or the cross-level patch of the region.
 template <typename T>
@@ -208,19 +176,6 @@ __device__ __forceinline__ T ext_value(const DevGrid<T>& g, int b, int x, int y,
   return g.patch[po + ((int64_t)(z - lz) * sy + (y - ly)) * sx + (x - lx)];
 }
 
-// ------------------------------------------------- zero-detail refinement
-// One workgroup per GItem.  LDS: coarse samples S, x-refined T1, y-refined T2.
-template <typename T, int N>
-__device__ __forceinline__ T refine_tap(const T* line, int stride, int p, int c0) {
-  // fine position p from coarse samples line[(c - c0)*stride]
-  if ((p & 1) == 0) return line[(floordiv(p, 2) - c0) * stride];
-  const int k = floordiv(p - 1, 2);
-  T acc = T(0);
-#pragma unroll
-  for (int i = 0; i < N; ++i) acc += T(DD<N>::w(i)) * line[(k + i + DD<N>::J0 - c0) * stride];
-  return acc;
-}
-
 // Owner-map cells of block m cached in LDS: leaf id, level, origin at its
 // level.  Turns a sample lookup into LDS reads plus one global load.
 struct CellTab {
@@ -246,42 +201,10 @@ __device__ __forceinline__ int wrap1(int X, int W) {
   return X;
 }
 
-// Value at the level-L point p (relative to block m at level L, origin O) of
-// the leaf holding it, by injection; p must lie on that leaf's grid and in
-// the half-block shell [-NB/2, 3NB/2)^3 covered by the owner map.
-template <typename T, int NB>
-__device__ __forceinline__ T cell_value(const DevGrid<T>& g, const CellTab& ct, int L, int Ox,
-                                        int Oy, int Oz, int px, int py, int pz) {
-  constexpr int H = NB / 2;
-  const unsigned ux = unsigned(px + H), uy = unsigned(py + H), uz = unsigned(pz + H);
-  if (ux >= 4u * H || uy >= 4u * H || uz >= 4u * H) {
-    atomicAdd(g.err, 1);
-    return T(0);
-  }
-  const int c = ((uz / H) * 4 + uy / H) * 4 + ux / H;
-  const int W = NB << L;
-  int X = wrap1(Ox + px, W), Y = wrap1(Oy + py, W), Z = wrap1(Oz + pz, W);
-  const int l = ct.lev[c];
-  if (l > L) {
-    X <<= 1; Y <<= 1; Z <<= 1;
-  } else if (l < L) {
-    if ((X | Y | Z) & 1) {
-      atomicAdd(g.err, 1);
-      return T(0);
-    }
-    X >>= 1; Y >>= 1; Z >>= 1;
-  }
-  const unsigned lx = unsigned(X - ct.ox[c]), ly = unsigned(Y - ct.oy[c]), lz = unsigned(Z - ct.oz[c]);
-  if (lx >= unsigned(NB) || ly >= unsigned(NB) || lz >= unsigned(NB)) {
-    atomicAdd(g.err, 1);
-    return T(0);
-  }
-  return g.field[(int64_t)ct.id[c] * (NB * NB * NB) + (lz * NB + ly) * NB + lx];
-}
-
-// Branch-free form of cell_value: the element index of the value (clamped into
-// the owning leaf) and a flag set when the point is outside the map or not on
-// the leaf's grid.  Lets a thread issue several loads before waiting on any.
+// Element index of the value of the leaf holding the level-L point p
+// (relative to block m at level L, origin O), by injection, clamped into that
+// leaf; *bad is set when p is outside the owner map or not on the leaf's grid.
+// Branch-free, so a thread can issue several loads before waiting on any.
 template <int NB>
 __device__ __forceinline__ int64_t cell_index(const CellTab& ct, int L, int Ox, int Oy, int Oz,
                                               int px, int py, int pz, int& bad) {
@@ -306,23 +229,6 @@ __device__ __forceinline__ int64_t cell_index(const CellTab& ct, int L, int Ox, 
   lz = min(lz, unsigned(NB - 1));
   return (int64_t)ct.id[c] * (NB * NB * NB) + int((lz * NB + ly) * NB + lx);
 }
-
-// Row iteration helper: rows of a 2D index space (a, b) in [0,na) x [0,nb_),
-// visited with stride `step` starting at `start`, without divisions.
-struct RowIt {
-  int a, b, na;
-  __device__ __forceinline__ RowIt(int start, int na_) : na(na_) {
-    a = start % na_;
-    b = start / na_;
-  }
-  __device__ __forceinline__ void advance(int step) {
-    a += step;
-    while (a >= na) {
-      a -= na;
-      ++b;
-    }
-  }
-};
 
 // Flattened iteration over a 3D box [0,w0) x [0,w1) x [0,w2) with a fixed
 // thread stride, carrying the coordinates incrementally (no divisions in the
@@ -415,7 +321,6 @@ __global__ __launch_bounds__(256) void k_gview(DevGrid<T> g, const GItem* __rest
   constexpr int HN = N / 2 - 1;   // index of sample c inside the window
   const GItem it = items[xcd_item(blockIdx.x, gridDim.x)];
   const int m = it.blk;
-  const int L = g.lev[m];
   const int tid = threadIdx.x, nt = blockDim.x;
   int clo[3], cs[3], fs[3], np[3], e[3];
 #pragma unroll
@@ -967,23 +872,6 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
 // Forward transform (x, then y, then z) of the ghost-filled block in FP64,
 // per-block maxima of |gamma| over 27 (x-class, y-class, z-class) boxes:
 // class 0 = [0, nb), 1 = [0, eb), 2 = [nb-ef, nb).
-template <int N, int NT, typename E>
-__device__ __forceinline__ double ana(const E* line, int stride, int p) {
-  // analysis at position p of a line whose element 0 is position (p - 0)...
-  // line points at position p; taps at line[o*stride]
-  double acc = 0.0;
-  if ((p & 1) == 0) {
-#pragma unroll
-    for (int o = -Ha<N, NT>::R; o <= Ha<N, NT>::R; ++o)
-      if (Ha<N, NT>::c(o) != 0.0) acc += Ha<N, NT>::c(o) * double(line[o * stride]);
-  } else {
-#pragma unroll
-    for (int o = -Ga<N>::R; o <= Ga<N>::R; ++o)
-      if (Ga<N>::c(o) != 0.0) acc += Ga<N>::c(o) * double(line[o * stride]);
-  }
-  return acc;
-}
-
 template <typename T, int NB, int N, int NT, int PF = 4>
 __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb,
                                                      double* __restrict__ bands,

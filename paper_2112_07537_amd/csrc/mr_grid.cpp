@@ -125,7 +125,6 @@ struct Lists {
   // classes <= 3, <= 6, <= 12 at [rcls[c], rcls[c+1]) with their LDS sizes
   int rcls[4] = {0, 0, 0, 0};
   int lds_rc[3] = {0, 0, 0};
-  int64_t scratch_elems = 0;
   int64_t out_points = 0;
   DevBuf dg, dr;
 };
@@ -178,7 +177,7 @@ struct mr_grid {
   // device
   std::vector<DevBuf> fields, alts;
   DevBuf tmpA, tmpB;
-  DevBuf d_lev, d_ijk, d_cmap, d_poff, d_patch, d_scratch, d_err, d_cbase, d_cstep;
+  DevBuf d_lev, d_ijk, d_cmap, d_poff, d_patch, d_err, d_cbase, d_cstep;
   DevBuf d_bands, d_norms, d_icpar, d_mom;
   Lists stage, wide;
   Prof prof;
@@ -425,7 +424,6 @@ static int Hreach(int N, int Nt) { return Nt ? N : 0; }
 static mr_status build_lists(mr_grid* g, int D, Lists& L) {
   L.g.clear();
   L.r.clear();
-  L.scratch_elems = 0;
   L.out_points = 0;
   const int nb = g->nb, N = g->N, Nt = g->Nt, Dw = g->Dw;
   const int H = Hreach(N, Nt);
@@ -669,8 +667,6 @@ static mr_status commit_tree_impl(mr_grid* g) {
   if (st != MR_OK) return st;
   st = build_lists(g, g->Dw, g->wide);
   if (st != MR_OK) return st;
-  const int64_t scr = std::max(g->stage.scratch_elems, g->wide.scratch_elems);
-  HIPCHK(g->d_scratch.ensure(std::max<int64_t>(1, scr) * g->esz));
   HIPCHK(hipStreamSynchronize(g->stream));  // host vectors above are staged
   ++g->tree_version;
   return MR_OK;
@@ -689,7 +685,6 @@ static DevGrid<T> view(mr_grid* g, void* field) {
   d.cstep = static_cast<const int32_t*>(g->d_cstep.p);
   d.field = static_cast<T*>(field);
   d.patch = static_cast<T*>(g->d_patch.p);
-  d.scratch = static_cast<T*>(g->d_scratch.p);
   d.dw = g->Dw;
   d.err = static_cast<int32_t*>(g->d_err.p);
   return d;
@@ -1327,7 +1322,7 @@ mr_status mr_grid_destroy(mr_grid* g) {
   for (auto& b : g->fields) b.release();
   for (auto& b : g->alts) b.release();
   DevBuf* bufs[] = {&g->tmpA, &g->tmpB, &g->d_lev, &g->d_ijk, &g->d_cmap, &g->d_poff, &g->d_patch,
-                    &g->d_scratch, &g->d_err, &g->d_bands, &g->d_norms, &g->d_icpar, &g->d_mom,
+                    &g->d_err, &g->d_bands, &g->d_norms, &g->d_icpar, &g->d_mom,
                     &g->stage.dg, &g->stage.dr, &g->wide.dg, &g->wide.dr, &g->ad_pairs,
                     &g->d_cbase, &g->d_cstep,
                     &g->ad_items, &g->ad_scr, &g->ad_det, &g->ad_slot};

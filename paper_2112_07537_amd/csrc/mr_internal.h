@@ -81,7 +81,6 @@ struct DevGrid {
   const int32_t* cstep;  //   (see k_cell_tables)
   T* field;              // [nblk * nb^3]
   T* patch;
-  T* scratch;
   int32_t dw;            // allocated depth of every patch region
   int32_t* err;          // device error counter (unsupported geometry)
 };
