@@ -868,11 +868,18 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
   }
 }
 
+// smallest v' >= v with v' = rem (mod m)
+constexpr int pad_to(int v, int m, int rem) { return v + ((rem - v % m) % m + m) % m; }
 // ------------------------------------------------------------------ details
 // Forward transform (x, then y, then z) of the ghost-filled block in FP64,
 // per-block maxima of |gamma| over 27 (x-class, y-class, z-class) boxes:
 // class 0 = [0, nb), 1 = [0, eb), 2 = [nb-ef, nb).
-template <typename T, int NB, int N, int NT, int PF = 4>
+// Planes are taken ZG at a time: every barrier phase (staging, x pass,
+// y pass) works on the whole group, so a plane costs 3/ZG barriers.  With
+// 24^3 blocks one workgroup fills a CU whatever its LDS (registers limit
+// it), so the group is 4 planes; smaller blocks keep it at 2 so that LDS
+// does not cap the workgroups per CU.
+template <typename T, int NB, int N, int NT, int ZG = (NB >= 24 ? 4 : 2), int PF = 4>
 __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb,
                                                      double* __restrict__ bands,
                                                      const int32_t* __restrict__ det_slot,
@@ -885,9 +892,20 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
   constexpr int P = NB + HF + HB;
   constexpr int LPT = (P * P + NB * NB - 1) / (NB * NB);
   constexpr int NP = NB / 2;
-  __shared__ double pl[P * P];      // input plane, converted once to FP64
-  __shared__ double t1[P * NB];     // after the x pass
-  __shared__ double t2[NB * NB];    // after the y pass
+  static_assert(PF >= ZG, "a group's planes are loaded before it starts");
+  // LDS layout, chosen so that the lanes of one access fall on distinct
+  // banks (32 banks of 4 bytes):
+  // * a staged plane is split into its even and odd x columns (x counted
+  //   from the block origin), so the x pass reads consecutive doubles;
+  //   rows of PH = NP (mod 16) doubles continue each other's banks, and
+  //   the odd half starts 8 doubles (16 banks) after the even half;
+  // * x-pass rows of NBS doubles, 2 NBS = NB (mod 16), for the y pass.
+  constexpr int PH = pad_to((P + 1) / 2, 16, NP % 16);
+  constexpr int PS = pad_to(P * PH, 16, 8);
+  constexpr int NBS = pad_to(NB, 8, (NB % 16) / 2);
+  __shared__ double pl[ZG][2 * PS];   // input planes in FP64: even, odd columns
+  __shared__ double t1[ZG][P * NBS];  // after the x pass
+  __shared__ double t2[ZG][NB * NB];  // after the y pass
   __shared__ Desc desc[27];
   __shared__ int nonfinite;
   // XCD-aware order: a block's halo is its Morton neighbours' data, which
@@ -907,13 +925,15 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
   // enters another z region (z < 0, [0, NB), >= NB).
   const T* kp[LPT];
   int32_t ksz[LPT];
-  int kx[LPT], ky[LPT];
+  int kx[LPT], ky[LPT], sidx[LPT];
 #pragma unroll
   for (int k = 0; k < LPT; ++k) {
     int i = tid + k * NB * NB;
     i = i < P * P ? i : P * P - 1;
     kx[k] = i % P - HF;
     ky[k] = i / P - HF;
+    const int c = i % P;   // column in the staged plane, x + HF
+    sidx[k] = ((c & 1) ^ (HF & 1) ? PS : 0) + (i / P) * PH + (c >> 1);
   }
   auto rebase = [&](int rz) {
 #pragma unroll
@@ -949,75 +969,103 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
     }
   }
 #pragma unroll
-  for (int zi = -HF; zi < NB + R; ++zi) {
-    T* cur = nx[(zi + HF) % PF];
-    double v = 0.0;
-    if (zi <= ZLAST) {
+  for (int z0 = -HF; z0 < NB + R; z0 += ZG) {
+    const bool live = z0 <= ZLAST;   // the group holds an input plane
+    // stage the group's planes in LDS, then reuse their load slots for the
+    // planes PF ahead (issued in z order: each re-base follows the last)
 #pragma unroll
-      for (int k = 0; k < LPT; ++k) {
-        const int i = tid + k * NB * NB;
-        if (k < LPT - 1 || i < P * P) pl[i] = double(cur[k]);
+    for (int q = 0; q < ZG; ++q) {
+      const int zi = z0 + q;
+      if (zi <= ZLAST) {
+        const T* cur = nx[(zi + HF) % PF];
+#pragma unroll
+        for (int k = 0; k < LPT; ++k) {
+          const int i = tid + k * NB * NB;
+          if (k < LPT - 1 || i < P * P) pl[q][sidx[k]] = double(cur[k]);
+        }
       }
-      __syncthreads();
-      if (zi + PF <= ZLAST) {
+    }
+    if (live) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < ZG; ++q) {
+      const int zi = z0 + q;
+      if (zi <= ZLAST && zi + PF <= ZLAST) {
         if (zreg(zi + PF) != zreg(zi + PF - 1)) rebase(zreg(zi + PF));
-        fetch(cur, zi + PF);
+        fetch(nx[(zi + HF) % PF], zi + PF);
       }
-      // x pass by pairs: H^a at the even point 2j, G^a at 2j+1 of each row
+    }
+    if (live) {
+      // x pass by pairs: H^a at the even point 2j, G^a at 2j+1 of each row,
+      // for every plane of the group
       for (int i = tid; i < P * NP; i += NB * NB) {
         const int j = i % NP, yy = i / NP;
-        const double* line = pl + yy * P + 2 * j + HF;
+#pragma unroll
+        for (int q = 0; q < ZG; ++q) {
+          if (z0 + q > ZLAST) continue;
+          // the value at x = 2j + d: even or odd half by the parity of d
+          const double* row = pl[q] + yy * PH + j;
+          auto at = [&](int d) {
+            return (d & 1) ? row[PS + ((d + HF) >> 1)] : row[(d + HF) >> 1];
+          };
+          double ev = 0.0, od = 0.0;
+#pragma unroll
+          for (int o = -HR; o <= HR; ++o)
+            if (Ha<N, NT>::c(o) != 0.0) ev += Ha<N, NT>::c(o) * at(o);
+#pragma unroll
+          for (int o = -GR; o <= GR; ++o)
+            if (Ga<N>::c(o) != 0.0) od += Ga<N>::c(o) * at(1 + o);
+          t1[q][yy * NBS + 2 * j] = ev;
+          t1[q][yy * NBS + 2 * j + 1] = od;
+        }
+      }
+      __syncthreads();
+      // y pass by pairs: (plane, column x, rows 2j (H^a) and 2j+1 (G^a))
+      for (int i = tid; i < ZG * NB * NP; i += NB * NB) {
+        const int q = i / (NB * NP), r = i % (NB * NP);
+        const int x = r % NB, j = r / NB;
+        if (z0 + q > ZLAST) continue;
+        const double* col = t1[q] + (2 * j + HF) * NBS + x;
         double ev = 0.0, od = 0.0;
 #pragma unroll
         for (int o = -HR; o <= HR; ++o)
-          if (Ha<N, NT>::c(o) != 0.0) ev += Ha<N, NT>::c(o) * line[o];
+          if (Ha<N, NT>::c(o) != 0.0) ev += Ha<N, NT>::c(o) * col[o * NBS];
 #pragma unroll
         for (int o = -GR; o <= GR; ++o)
-          if (Ga<N>::c(o) != 0.0) od += Ga<N>::c(o) * line[1 + o];
-        t1[yy * NB + 2 * j] = ev;
-        t1[yy * NB + 2 * j + 1] = od;
+          if (Ga<N>::c(o) != 0.0) od += Ga<N>::c(o) * col[(1 + o) * NBS];
+        t2[q][2 * j * NB + x] = ev;
+        t2[q][(2 * j + 1) * NB + x] = od;
       }
       __syncthreads();
-      // y pass by pairs: column x, rows 2j (H^a) and 2j+1 (G^a)
-      if (tid < NB * NP) {
-        const int x = tid % NB, j = tid / NB;
-        const double* col = t1 + (2 * j + HF) * NB + x;
-        double ev = 0.0, od = 0.0;
-#pragma unroll
-        for (int o = -HR; o <= HR; ++o)
-          if (Ha<N, NT>::c(o) != 0.0) ev += Ha<N, NT>::c(o) * col[o * NB];
-#pragma unroll
-        for (int o = -GR; o <= GR; ++o)
-          if (Ga<N>::c(o) != 0.0) od += Ga<N>::c(o) * col[(1 + o) * NB];
-        t2[2 * j * NB + x] = ev;
-        t2[(2 * j + 1) * NB + x] = od;
-      }
-      __syncthreads();
-      v = t2[ty * NB + tx];
     }
+    // z pass over the group's planes, in order, through the register ring
 #pragma unroll
-    for (int i = 0; i < 2 * R; ++i) ring[i] = ring[i + 1];
-    ring[2 * R] = v;
-    const int zo = zi - R;
-    if (zo >= 0 && zo < NB) {
-      double gsum = 0.0;
-      if ((zo & 1) == 0) {
+    for (int q = 0; q < ZG; ++q) {
+      const int zi = z0 + q;
+      const double v = zi <= ZLAST ? t2[q][ty * NB + tx] : 0.0;
 #pragma unroll
-        for (int o = -HR; o <= HR; ++o)
-          if (Ha<N, NT>::c(o) != 0.0) gsum += Ha<N, NT>::c(o) * ring[R + o];
-      } else {
+      for (int i = 0; i < 2 * R; ++i) ring[i] = ring[i + 1];
+      ring[2 * R] = v;
+      const int zo = zi - R;
+      if (zo >= 0 && zo < NB) {
+        double gsum = 0.0;
+        if ((zo & 1) == 0) {
 #pragma unroll
-        for (int o = -GR; o <= GR; ++o)
-          if (Ga<N>::c(o) != 0.0) gsum += Ga<N>::c(o) * ring[R + o];
+          for (int o = -HR; o <= HR; ++o)
+            if (Ha<N, NT>::c(o) != 0.0) gsum += Ha<N, NT>::c(o) * ring[R + o];
+        } else {
+#pragma unroll
+          for (int o = -GR; o <= GR; ++o)
+            if (Ga<N>::c(o) != 0.0) gsum += Ga<N>::c(o) * ring[R + o];
+        }
+        const bool isdet = (zo & 1) != 0 || ((tx | ty) & 1) != 0;
+        const double a = isdet ? fabs(gsum) : 0.0;
+        bad = bad || !(a <= 1e300);
+        m0 = fmax(m0, a);
+        if (zo < eb) m1 = fmax(m1, a);
+        if (zo >= NB - ef) m2 = fmax(m2, a);
+        if (slot >= 0)
+          det_out[(int64_t)slot * NB * NB * NB + ((int64_t)zo * NB + ty) * NB + tx] = isdet ? gsum : 0.0;
       }
-      const bool isdet = (zo & 1) != 0 || ((tx | ty) & 1) != 0;
-      const double a = isdet ? fabs(gsum) : 0.0;
-      bad = bad || !(a <= 1e300);
-      m0 = fmax(m0, a);
-      if (zo < eb) m1 = fmax(m1, a);
-      if (zo >= NB - ef) m2 = fmax(m2, a);
-      if (slot >= 0)
-        det_out[(int64_t)slot * NB * NB * NB + ((int64_t)zo * NB + ty) * NB + tx] = isdet ? gsum : 0.0;
     }
   }
   // Fold the column maxima into the 27 boxes (x-class, y-class, z-class;
@@ -1025,9 +1073,9 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
   // per row and x-class, then per box over the rows of its y-class.
   // (No LDS atomics: a contended atomic max is expanded into a per-lane
   // loop.)  The buffers of the plane loop are free by now.
-  double* colmax = pl;                 // [ty][tx] for one z-class
-  double* rowmax = t1;                 // [cz][ty][cx]
-  static_assert(P * P >= NB * NB && P * NB >= NB * 9, "reduction buffers");
+  double* colmax = pl[0];              // [ty][tx] for one z-class
+  double* rowmax = t1[0];              // [cz][ty][cx]
+  static_assert(2 * PS >= NB * NB && P * NBS >= NB * 9, "reduction buffers");
   if (bad) nonfinite = 1;
   const double mz[3] = {m0, m1, m2};
 #pragma unroll
