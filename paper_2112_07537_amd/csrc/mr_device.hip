@@ -1070,33 +1070,42 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
   }
   // Fold the column maxima into the 27 boxes (x-class, y-class, z-class;
   // class 0 = [0, nb), 1 = [0, eb), 2 = [nb-ef, nb)) in two LDS stages:
-  // per row and x-class, then per box over the rows of its y-class.
-  // (No LDS atomics: a contended atomic max is expanded into a per-lane
-  // loop.)  The buffers of the plane loop are free by now.
-  double* colmax = pl[0];              // [ty][tx] for one z-class
-  double* rowmax = t1[0];              // [cz][ty][cx]
-  static_assert(2 * PS >= NB * NB && P * NBS >= NB * 9, "reduction buffers");
+  // per (z-class, row, x-class), then per box over the rows of its y-class.
+  // Both folds run over the whole extent with a mask, fully unrolled, so
+  // their LDS reads are issued back to back.  (No LDS atomics: a contended
+  // atomic max is expanded into a per-lane loop.)  The buffers of the plane
+  // loop are free once every thread has passed the first barrier below.
+  double* colmax = &pl[0][0];          // [cz][ty][tx]
+  double* rowmax = &t1[0][0];          // [cz][ty][cx]
+  static_assert(ZG * 2 * PS >= 3 * NB * NB && ZG * P * NBS >= 9 * NB, "reduction buffers");
   if (bad) nonfinite = 1;
-  const double mz[3] = {m0, m1, m2};
+  __syncthreads();
+  colmax[tid] = m0;
+  colmax[NB * NB + tid] = m1;
+  colmax[2 * NB * NB + tid] = m2;
+  __syncthreads();
+  for (int i = tid; i < 9 * NB; i += NB * NB) {   // i = (cz * NB + y) * 3 + cx
+    const int cx = i % 3, y = (i / 3) % NB, cz = i / (3 * NB);
+    const int x0 = cx == 2 ? NB - ef : 0, x1 = cx == 1 ? eb : NB;
+    const double* row = colmax + (cz * NB + y) * NB;
+    double v = 0.0;
 #pragma unroll
-  for (int cz = 0; cz < 3; ++cz) {
-    __syncthreads();
-    colmax[ty * NB + tx] = mz[cz];
-    __syncthreads();
-    if (tid < NB * 3) {
-      const int y = tid / 3, cx = tid % 3;
-      const int x0 = cx == 2 ? NB - ef : 0, x1 = cx == 1 ? eb : NB;
-      double v = 0.0;
-      for (int x = x0; x < x1; ++x) v = fmax(v, colmax[y * NB + x]);
-      rowmax[(cz * NB + y) * 3 + cx] = v;
+    for (int x = 0; x < NB; ++x) {
+      const double w = row[x];
+      v = (x >= x0 && x < x1) ? fmax(v, w) : v;
     }
+    rowmax[i] = v;
   }
   __syncthreads();
   if (tid < 27) {
     const int cx = tid % 3, cy = (tid / 3) % 3, cz = tid / 9;
     const int y0 = cy == 2 ? NB - ef : 0, y1 = cy == 1 ? eb : NB;
     double v = 0.0;
-    for (int y = y0; y < y1; ++y) v = fmax(v, rowmax[(cz * NB + y) * 3 + cx]);
+#pragma unroll
+    for (int y = 0; y < NB; ++y) {
+      const double w = rowmax[(cz * NB + y) * 3 + cx];
+      v = (y >= y0 && y < y1) ? fmax(v, w) : v;
+    }
     if (nonfinite) v = __longlong_as_double(0x7ff8000000000000ll);
     bands[(int64_t)b * 27 + tid] = v;
   }
