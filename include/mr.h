@@ -166,6 +166,20 @@ mr_status mr_adapt(mr_grid* g, int32_t field, int32_t max_iter, mr_adapt_stats* 
  * advection; each stage reconstructs the ghosts first.  Asynchronous. */
 mr_status mr_rk3_step(mr_grid* g, int32_t field, double dt, const mr_velocity* vel);
 
+/* Fused step: the block criterion of `field` (as mr_details), then one
+ * SSP-RK3 step of it (as mr_rk3_step), whose first stage uses the ghosts
+ * that the criterion's wide reconstruction (section 2.2.5, Table 3) has
+ * just made for the same values; only stages 2 and 3 reconstruct theirs.
+ * The norms are those of the field before the step.  Results equal
+ * mr_details followed by mr_rk3_step up to the rounding order of the f->c
+ * ghost values (the restriction tiles differ with the ghost depth).
+ * norms, on_device: as in mr_details; with on_device = 0 the call
+ * synchronises, and MR_ENONFINITE is returned after the step has been
+ * applied.  Asynchronous with on_device = 1; captured into a graph of its
+ * own in graph execution mode. */
+mr_status mr_details_rk3_step(mr_grid* g, int32_t field, double dt, const mr_velocity* vel,
+                              double* norms, int32_t on_device);
+
 /* dt = cfl * h_min / max_x sum_d |u_d(x)| for the current tree. */
 mr_status mr_cfl_dt(const mr_grid* g, const mr_velocity* vel, double cfl, double* dt);
 

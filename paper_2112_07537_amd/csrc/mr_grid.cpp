@@ -181,13 +181,24 @@ struct mr_grid {
   DevBuf d_bands, d_norms, d_icpar, d_mom;
   Lists stage, wide;
   Prof prof;
-  // hipGraph of a whole RK3 step
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  double g_dt = 0;
-  mr_velocity g_vel{};
-  int g_field = -1;
-  int64_t tree_version = 0, graph_version = -1;
+  // hipGraphs of a whole RK3 step and of a fused detail pass + RK3 step,
+  // each re-captured when the tree, the field, dt or the velocity changes
+  struct StepGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double dt = 0;
+    mr_velocity vel{};
+    int field = -1;
+    int64_t version = -1;
+    void reset() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      exec = nullptr;
+      graph = nullptr;
+    }
+  };
+  StepGraph rk3_graph, fused_graph;
+  int64_t tree_version = 0;
 };
 
 namespace mr {
@@ -1200,16 +1211,57 @@ static double usum(const mr_velocity& v) {
   return std::fabs(v.p[0]) + std::fabs(v.p[1]) + std::fabs(v.p[2]);
 }
 
-static void enqueue_rk3(mr_grid* g, int field, double dt, const VelDev& vd) {
+// One SSP-RK3 step.  With `filled`, the ghosts of the field are already
+// those of a wide reconstruction of its current values (a detail pass just
+// before): its patches hold every value of the stage depth, so the first
+// stage does not reconstruct them again.
+static void enqueue_rk3(mr_grid* g, int field, double dt, const VelDev& vd, bool filled = false) {
   void* u = g->fields[field].p;
   void* A = g->tmpA.p;
   void* B = g->tmpB.p;
-  ghost_fill(g, u, g->stage);
+  if (!filled) ghost_fill(g, u, g->stage);
   rhs_stage(g, u, u, A, 0.0, 1.0, dt, vd);
   ghost_fill(g, A, g->stage);
   rhs_stage(g, A, u, B, 0.75, 0.25, dt, vd);
   ghost_fill(g, B, g->stage);
   rhs_stage(g, B, u, u, 1.0 / 3.0, 2.0 / 3.0, dt, vd);
+}
+
+static mr_status check_step_args(mr_grid* g, int32_t field, double dt, const mr_velocity* vel,
+                                 VelDev& vd) {
+  if (!g || !vel || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(MR_EINVAL, "dt must be positive");
+  if (vel->kind < 0 || vel->kind > 2) return fail(MR_EINVAL, "unknown velocity kind");
+  vd = VelDev{};
+  vd.kind = vel->kind;
+  for (int i = 0; i < 8; ++i) vd.p[i] = vel->p[i];
+  return MR_OK;
+}
+
+// Enqueue `work` on the grid's stream, through a captured graph in graph
+// mode (re-captured when the tree, the field, dt or the velocity changed).
+template <typename F>
+static mr_status run_step(mr_grid* g, mr_grid::StepGraph& sg, int32_t field, double dt,
+                          const mr_velocity* vel, F&& work) {
+  if (g->cfg.exec_mode == 2 && !g->prof.on) {
+    const bool same = sg.exec && sg.version == g->tree_version && sg.dt == dt &&
+                      sg.field == field && std::memcmp(&sg.vel, vel, sizeof(mr_velocity)) == 0;
+    if (!same) {
+      sg.reset();
+      HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+      work();
+      HIPCHK(hipStreamEndCapture(g->stream, &sg.graph));
+      HIPCHK(hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0));
+      sg.version = g->tree_version;
+      sg.dt = dt;
+      sg.field = field;
+      sg.vel = *vel;
+    }
+    HIPCHK(hipGraphLaunch(sg.exec, g->stream));
+    return MR_OK;
+  }
+  work();
+  return MR_OK;
 }
 
 }  // namespace mr
@@ -1313,8 +1365,8 @@ mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, mr_grid** out) 
 mr_status mr_grid_destroy(mr_grid* g) {
   if (!g) return fail(MR_EINVAL, "null grid");
   (void)hipStreamSynchronize(g->stream);
-  if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
-  if (g->graph) (void)hipGraphDestroy(g->graph);
+  g->rk3_graph.reset();
+  g->fused_graph.reset();
   for (auto& r : g->prof.recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -1463,33 +1515,36 @@ mr_status mr_adapt(mr_grid* g, int32_t field, int32_t max_iter, mr_adapt_stats* 
 }
 
 mr_status mr_rk3_step(mr_grid* g, int32_t field, double dt, const mr_velocity* vel) {
-  if (!g || !vel || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
-  if (!(dt > 0) || !std::isfinite(dt)) return fail(MR_EINVAL, "dt must be positive");
-  if (vel->kind < 0 || vel->kind > 2) return fail(MR_EINVAL, "unknown velocity kind");
-  VelDev vd{};
-  vd.kind = vel->kind;
-  for (int i = 0; i < 8; ++i) vd.p[i] = vel->p[i];
-  if (g->cfg.exec_mode == 2 && !g->prof.on) {
-    const bool same = g->gexec && g->graph_version == g->tree_version && g->g_dt == dt &&
-                      g->g_field == field && std::memcmp(&g->g_vel, vel, sizeof(mr_velocity)) == 0;
-    if (!same) {
-      if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
-      if (g->graph) (void)hipGraphDestroy(g->graph);
-      g->gexec = nullptr;
-      g->graph = nullptr;
-      HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
-      enqueue_rk3(g, field, dt, vd);
-      HIPCHK(hipStreamEndCapture(g->stream, &g->graph));
-      HIPCHK(hipGraphInstantiate(&g->gexec, g->graph, nullptr, nullptr, 0));
-      g->graph_version = g->tree_version;
-      g->g_dt = dt;
-      g->g_field = field;
-      g->g_vel = *vel;
-    }
-    HIPCHK(hipGraphLaunch(g->gexec, g->stream));
+  VelDev vd;
+  mr_status st = check_step_args(g, field, dt, vel, vd);
+  if (st != MR_OK) return st;
+  return run_step(g, g->rk3_graph, field, dt, vel, [&] { enqueue_rk3(g, field, dt, vd); });
+}
+
+mr_status mr_details_rk3_step(mr_grid* g, int32_t field, double dt, const mr_velocity* vel,
+                              double* norms, int32_t on_device) {
+  VelDev vd;
+  mr_status st = check_step_args(g, field, dt, vel, vd);
+  if (st != MR_OK) return st;
+  if (!norms && !on_device) return fail(MR_EINVAL, "bad argument");
+  st = run_step(g, g->fused_graph, field, dt, vel, [&] {
+    void* u = g->fields[field].p;
+    ghost_fill(g, u, g->wide);
+    details_pass(g, u, nullptr, nullptr);
+    enqueue_rk3(g, field, dt, vd, true);
+  });
+  if (st != MR_OK) return st;
+  const size_t n = g->leaves.size();
+  if (on_device) {
+    if (norms && n)
+      HIPCHK(hipMemcpyAsync(norms, g->d_norms.p, n * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
     return MR_OK;
   }
-  enqueue_rk3(g, field, dt, vd);
+  HIPCHK(hipMemcpyAsync(norms, g->d_norms.p, n * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+  st = check_err(g);
+  if (st != MR_OK) return st;
+  for (size_t b = 0; b < n; ++b)
+    if (!std::isfinite(norms[b])) return fail(MR_ENONFINITE, "non-finite detail norm");
   return MR_OK;
 }
 

@@ -62,6 +62,7 @@ def load():
         "mr_details": [P, C.c_int32, P, C.c_int32],
         "mr_adapt": [P, C.c_int32, C.c_int32, C.POINTER(mr_adapt_stats)],
         "mr_rk3_step": [P, C.c_int32, C.c_double, C.POINTER(mr_velocity)],
+        "mr_details_rk3_step": [P, C.c_int32, C.c_double, C.POINTER(mr_velocity), P, C.c_int32],
         "mr_cfl_dt": [P, C.POINTER(mr_velocity), C.c_double, C.POINTER(C.c_double)],
         "mr_block_meta": [P, C.c_int64, C.POINTER(C.c_int64), P, P],
         "mr_field_get": [P, C.c_int32, P, C.c_size_t],
@@ -224,6 +225,17 @@ class Grid:
 
     def rk3_step(self, dt, vel, field=0):
         _check(lib().mr_rk3_step(self._h, field, dt, C.byref(vel)))
+
+    def details_rk3_step(self, dt, vel, field=0):
+        """Detail norms of the field, then one RK3 step that reuses their
+        ghosts for its first stage; returns the norms (before the step)."""
+        n = self.n_blocks()
+        a = np.empty(n, np.float64)
+        _check(lib().mr_details_rk3_step(self._h, field, dt, C.byref(vel), _ptr(a), 0))
+        return a
+
+    def details_rk3_step_async(self, dt, vel, dev_ptr=None, field=0):
+        _check(lib().mr_details_rk3_step(self._h, field, dt, C.byref(vel), C.c_void_p(dev_ptr), 1))
 
     def cfl_dt(self, vel, cfl):
         dt = C.c_double()

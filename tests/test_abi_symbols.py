@@ -69,3 +69,7 @@ def test_validation_errors_without_device(lib):
         f = getattr(lib, name)
         f.restype = C.c_int32
         assert f(*args) == mr.MR_EINVAL, name
+    f = lib.mr_details_rk3_step
+    f.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.c_int32]
+    f.restype = C.c_int32
+    assert f(None, 0, 0.1, None, None, 1) == mr.MR_EINVAL
