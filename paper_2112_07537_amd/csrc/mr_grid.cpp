@@ -639,17 +639,30 @@ static mr_status commit_tree_impl(mr_grid* g) {
   if (st != MR_OK) return st;
   const int n = int(g->leaves.size());
   const int nb = g->nb, Dw = g->Dw;
+  // patch offsets: per-block patch sizes on host threads, then a prefix sum
   g->poff.assign(size_t(n) * 27, -1);
-  int64_t cur = 0;
-  for (int b = 0; b < n; ++b)
-    for (int r = 0; r < 27; ++r) {
-      if (r == 13) continue;
-      if (region_level(g, b, r) == g->leaves[b].L) continue;
-      int lo[3], hi[3];
-      region_box(nb, Dw, r, lo, hi);
-      g->poff[size_t(b) * 27 + r] = cur;
-      cur += box_size(lo, hi);
+  std::vector<int64_t> bsize(n);
+  parallel_for(size_t(n), [&](size_t lo_b, size_t hi_b) {
+    for (size_t b = lo_b; b < hi_b; ++b) {
+      int64_t sz = 0;
+      for (int r = 0; r < 27; ++r) {
+        if (r == 13 || region_level(g, int(b), r) == g->leaves[b].L) continue;
+        int lo[3], hi[3];
+        region_box(nb, Dw, r, lo, hi);
+        g->poff[b * 27 + r] = sz;   // offset inside the block's patches
+        sz += box_size(lo, hi);
+      }
+      bsize[b] = sz;
     }
+  });
+  int64_t cur = 0;
+  for (int b = 0; b < n; ++b) {
+    const int64_t base = cur;
+    cur += bsize[b];
+    if (bsize[b] == 0) continue;
+    for (int r = 0; r < 27; ++r)
+      if (g->poff[size_t(b) * 27 + r] >= 0) g->poff[size_t(b) * 27 + r] += base;
+  }
   g->patch_elems = cur;
   std::vector<int32_t> lev(n), ijk(3 * size_t(n));
   for (int b = 0; b < n; ++b) {
