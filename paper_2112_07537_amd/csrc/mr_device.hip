@@ -813,8 +813,10 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
   const int64_t obase = (int64_t)b * nb3 + (int64_t)ty * NB + tx;
   const T ux_y = vx_z[ty];  // rotating: u_x = -(y - cy) (per y); shear: per z
   // u^n is also read one plane ahead, before that plane's stencil loads, so
-  // waiting for it never drains the loads issued later
-  T ucur = un[obase];
+  // waiting for it never drains the loads issued later.  u^n and the output
+  // are touched once per point: non-temporal accesses leave more of L2 to
+  // the stage input, whose rows are read again as the neighbours' halos.
+  T ucur = __builtin_nontemporal_load(&un[obase]);
   // fully unrolled: the register rotations below become renames, so the
   // loads issued for later planes stay in flight across iterations
 #pragma unroll
@@ -824,7 +826,7 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
     for (int k = 0; k < HPT; ++k)
       if (hh[k]) plane[(hy[k] + G) * P + hx[k] + G] = hval[k];
     const T u0 = ucur;
-    if (z + 1 < NB) ucur = un[obase + (int64_t)(z + 1) * NB * NB];  // stage 1 passes its input
+    if (z + 1 < NB) ucur = __builtin_nontemporal_load(&un[obase + (int64_t)(z + 1) * NB * NB]);
     T pf2 = T(0), hv2[HPT];
     if (z + G + 2 < NB + G) pf2 = load(tx, ty, z + G + 2);
 #pragma unroll
@@ -854,7 +856,7 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
     }
     const T rhs = -(ux * dx + uy * dy + uz * dz) * T(inv_h);
     const T yv = col[G];
-    out[obase + (int64_t)z * NB * NB] = a_un * u0 + b_y * (yv + dt * rhs);
+    __builtin_nontemporal_store(a_un * u0 + b_y * (yv + dt * rhs), &out[obase + (int64_t)z * NB * NB]);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 2 * G; ++i) col[i] = col[i + 1];
