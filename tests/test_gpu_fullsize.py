@@ -8,6 +8,7 @@
   the detail norms with the oracle's per-block transform.
 * Property at any size: one FP32 RK3 step against one FP64 RK3 step from the
   same (upcast) state differs by at most 1e-5 of max|phi|.
+* The fused detail pass + RK3 step against the two separate calls.
 * Batched launches, plain per-block launches and the hipGraph-captured step
   give identical results; the graph is replayed several times with eager work
   and synchronisations in between, each replay checked.
@@ -158,6 +159,38 @@ def test_fullsize_fp32_step_vs_fp64(fullsize):
     g64.close()
     scale = np.abs(b).max()
     assert np.abs(a - b).max() <= 1e-5 * scale
+
+
+def test_fullsize_fused_matches_separate_calls(fullsize):
+    """mr_details_rk3_step against mr_details + mr_rk3_step from the same
+    state, at the benchmark size: the norms agree, and the fields after the
+    step agree to the parity tolerance (only the rounding order of f->c
+    ghost values may differ)."""
+    cfg, g = fullsize
+    keys = g.block_meta()
+    data = g.field_get()
+    pair = []
+    for _ in range(2):
+        h = mr.Grid(cfg["nb"], cfg["N"], cfg["Nt"], fd_order=cfg["fd"],
+                    level_min=cfg["level_min"], level_max=cfg["level_max"], prec=cfg["prec"],
+                    eps_refine=cfg["eps_refine"], eps_coarsen=cfg["eps_coarsen"],
+                    max_blocks=150000)
+        h.set_tree(keys)
+        h.field_set(data)
+        pair.append(h)
+    a, b = pair
+    kind, p = wl.velocity_spec(cfg["vel"])
+    v = mr.velocity(kind, *p)
+    dt = a.cfl_dt(v, cfg["cfl"])
+    na = a.details_rk3_step(dt, v)
+    nb_ = b.details()
+    b.rk3_step(dt, v)
+    tol = (1e-12 if cfg["prec"] == "f64" else 1e-5) * np.abs(data).max()
+    assert np.abs(na - nb_).max() <= tol
+    err = np.abs(a.field_get().astype(np.float64) - b.field_get()).max()
+    a.close()
+    b.close()
+    assert err <= tol, err
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
