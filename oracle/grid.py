@@ -5,8 +5,8 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 with the HIP path; both sides read the same seeded inputs only.
 
 Source: Gillis & van Rees, "MURPHY" (arXiv 2112.07537).  Each function names
-the passage it follows.  Readings of passages that are silent or ambiguous are
-marked READING and listed in the design doc.
+the passage it follows.  Where a passage is silent or ambiguous, the reading
+taken is marked READING at the place it is used.
 
 Geometry (READING, node-based left-aligned points): periodic unit cube, one
 tree, root level 0.  Leaf (L, i, j, k) holds nb^3 points; local point (x,y,z)
