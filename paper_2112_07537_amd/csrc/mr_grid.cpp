@@ -162,6 +162,10 @@ struct mr_grid {
   mr_config cfg{};
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // second stream (default priority) for the detail pass of a fused step,
+  // which runs beside the first stage's RHS; fork / join events
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   HostTimer htime;
   DevBuf ad_pairs, ad_items, ad_scr, ad_det, ad_slot;   // adaptation scratch
   bool f32 = false;
@@ -804,7 +808,9 @@ static void rhs_stage(mr_grid* g, void* y, const void* un, void* out, double a_u
   prof_end(g, 0, a, e, !plain, int64_t(n) * g->nb * g->nb * g->nb);
 }
 
-static void details_pass(mr_grid* g, void* field, const int32_t* det_slot, double* det_out) {
+static void details_pass(mr_grid* g, void* field, const int32_t* det_slot, double* det_out,
+                         hipStream_t st = nullptr) {
+  const hipStream_t strm = st ? st : g->stream;
   AnyView v = anyview(g, field);
   const int n = int(g->leaves.size());
   const Wavelet w{g->N, g->Nt};
@@ -814,14 +820,14 @@ static void details_pass(mr_grid* g, void* field, const int32_t* det_slot, doubl
   if (plain) {
     for (int b = 0; b < n; ++b)
       launch_details(g->f32, v.raw, w, g->Ef, g->Eb, static_cast<double*>(g->d_bands.p), det_slot,
-                     det_out, b, 1, g->stream);
+                     det_out, b, 1, strm);
   } else {
     launch_details(g->f32, v.raw, w, g->Ef, g->Eb, static_cast<double*>(g->d_bands.p), det_slot,
-                   det_out, 0, n, g->stream);
+                   det_out, 0, n, strm);
   }
   prof_end(g, 1, a, e, !plain, int64_t(n) * g->nb * g->nb * g->nb);
   launch_combine(v.raw, static_cast<double*>(g->d_bands.p), g->cfg.detail_ext,
-                 static_cast<double*>(g->d_norms.p), n, g->stream);
+                 static_cast<double*>(g->d_norms.p), n, strm);
 }
 
 static mr_status check_err(mr_grid* g) {
@@ -1227,13 +1233,17 @@ static double usum(const mr_velocity& v) {
 // One SSP-RK3 step.  With `filled`, the ghosts of the field are already
 // those of a wide reconstruction of its current values (a detail pass just
 // before): its patches hold every value of the stage depth, so the first
-// stage does not reconstruct them again.
-static void enqueue_rk3(mr_grid* g, int field, double dt, const VelDev& vd, bool filled = false) {
+// stage does not reconstruct them again.  `join`, if given, is an event the
+// second reconstruction must wait for: it overwrites the patches, which
+// work on another stream may still be reading.
+static void enqueue_rk3(mr_grid* g, int field, double dt, const VelDev& vd, bool filled = false,
+                        hipEvent_t join = nullptr) {
   void* u = g->fields[field].p;
   void* A = g->tmpA.p;
   void* B = g->tmpB.p;
   if (!filled) ghost_fill(g, u, g->stage);
   rhs_stage(g, u, u, A, 0.0, 1.0, dt, vd);
+  if (join) (void)hipStreamWaitEvent(g->stream, join, 0);
   ghost_fill(g, A, g->stage);
   rhs_stage(g, A, u, B, 0.75, 0.25, dt, vd);
   ghost_fill(g, B, g->stage);
@@ -1277,6 +1287,33 @@ static mr_status run_step(mr_grid* g, mr_grid::StepGraph& sg, int32_t field, dou
   return MR_OK;
 }
 
+// Release everything a grid holds (also on the error paths of creation).
+static void free_grid(mr_grid* g) {
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  if (g->aux) (void)hipStreamSynchronize(g->aux);
+  g->rk3_graph.reset();
+  g->fused_graph.reset();
+  for (auto& r : g->prof.recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto& b : g->fields) b.release();
+  for (auto& b : g->alts) b.release();
+  DevBuf* bufs[] = {&g->tmpA, &g->tmpB, &g->d_lev, &g->d_ijk, &g->d_cmap, &g->d_poff, &g->d_patch,
+                    &g->d_err, &g->d_bands, &g->d_norms, &g->d_icpar, &g->d_mom,
+                    &g->stage.dg, &g->stage.dr, &g->wide.dg, &g->wide.dr, &g->ad_pairs,
+                    &g->d_cbase, &g->d_cstep,
+                    &g->ad_items, &g->ad_scr, &g->ad_det, &g->ad_slot};
+  for (DevBuf* b : bufs) b->release();
+  if (g->aux) {
+    (void)hipEventDestroy(g->ev_fork);
+    (void)hipEventDestroy(g->ev_join);
+    (void)hipStreamDestroy(g->aux);
+  }
+  if (g->own_stream) (void)hipStreamDestroy(g->stream);
+  delete g;
+}
+
 }  // namespace mr
 
 // =================================================================== C ABI
@@ -1308,10 +1345,20 @@ mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, mr_grid** out) 
     // a private non-blocking stream (default priority): the legacy NULL
     // stream cannot be captured into a graph
     if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) {
-      delete g;
+      free_grid(g);
       return fail(MR_EHIP, "hipStreamCreateWithFlags failed");
     }
     g->own_stream = true;
+  }
+  if (hipStreamCreateWithFlags(&g->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming) != hipSuccess) {
+    // without them the fused step runs its detail pass in order
+    if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
+    if (g->aux) (void)hipStreamDestroy(g->aux);
+    g->aux = nullptr;
+    g->ev_fork = g->ev_join = nullptr;
+    (void)hipGetLastError();
   }
   g->f32 = c.prec == MR_F32;
   g->esz = g->f32 ? 4 : 8;
@@ -1331,7 +1378,7 @@ mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, mr_grid** out) 
   // points beyond the block
   if (2 * ((g->Dw + 1) / 2 + g->N / 2) > g->nb / 2) {
     const int Dw = g->Dw;
-    delete g;
+    free_grid(g);
     return fail(MR_EINVAL, "nb too small for this wavelet: ghost depth " + std::to_string(Dw) +
                                " plus the refinement reach must fit in nb/2");
   }
@@ -1341,17 +1388,17 @@ mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, mr_grid** out) 
   if (c.eps_refine / std::max(c.eps_coarsen, 1e-300) <= double(1 << g->N))
     warn = "warning: eps_refine/eps_coarsen <= 2^N may flip-flop (section 2.2.5)";
   if (g->d_err.ensure(sizeof(int32_t)) != hipSuccess || g->d_mom.ensure(4 * sizeof(double)) != hipSuccess) {
-    delete g;
+    free_grid(g);
     return fail(MR_ENOMEM, "device allocation failed");
   }
   int32_t z = 0;
   if (hipMemcpy(g->d_err.p, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) {
-    delete g;
+    free_grid(g);
     return fail(MR_EHIP, "hipMemcpy failed");
   }
   mr_status st = ensure_fields(g);
   if (st != MR_OK) {
-    delete g;
+    free_grid(g);
     return fail(MR_ENOMEM, "field allocation failed: " + g_errmsg);
   }
   const int n = 1 << c.level_min;
@@ -1361,13 +1408,13 @@ mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, mr_grid** out) 
   sort_leaves(g->leaves);
   st = commit_tree(g);
   if (st != MR_OK) {
-    delete g;
+    free_grid(g);
     return st;
   }
   for (int f = 0; f < c.n_fields; ++f)
     launch_fill(g->f32, g->fields[f].p, g->leaves.size() * size_t(g->nb * g->nb * g->nb), g->stream);
   if (hipStreamSynchronize(g->stream) != hipSuccess) {
-    delete g;
+    free_grid(g);
     return fail(MR_EHIP, "stream synchronize failed");
   }
   *out = g;
@@ -1377,23 +1424,7 @@ mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, mr_grid** out) 
 
 mr_status mr_grid_destroy(mr_grid* g) {
   if (!g) return fail(MR_EINVAL, "null grid");
-  (void)hipStreamSynchronize(g->stream);
-  g->rk3_graph.reset();
-  g->fused_graph.reset();
-  for (auto& r : g->prof.recs) {
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
-  }
-  for (auto& b : g->fields) b.release();
-  for (auto& b : g->alts) b.release();
-  DevBuf* bufs[] = {&g->tmpA, &g->tmpB, &g->d_lev, &g->d_ijk, &g->d_cmap, &g->d_poff, &g->d_patch,
-                    &g->d_err, &g->d_bands, &g->d_norms, &g->d_icpar, &g->d_mom,
-                    &g->stage.dg, &g->stage.dr, &g->wide.dg, &g->wide.dr, &g->ad_pairs,
-                    &g->d_cbase, &g->d_cstep,
-                    &g->ad_items, &g->ad_scr, &g->ad_det, &g->ad_slot};
-  for (DevBuf* b : bufs) b->release();
-  if (g->own_stream) (void)hipStreamDestroy(g->stream);
-  delete g;
+  free_grid(g);
   return MR_OK;
 }
 
@@ -1543,8 +1574,20 @@ mr_status mr_details_rk3_step(mr_grid* g, int32_t field, double dt, const mr_vel
   st = run_step(g, g->fused_graph, field, dt, vel, [&] {
     void* u = g->fields[field].p;
     ghost_fill(g, u, g->wide);
-    details_pass(g, u, nullptr, nullptr);
-    enqueue_rk3(g, field, dt, vd, true);
+    // The detail pass and the first stage's RHS both only read the field and
+    // its patches (and write disjoint buffers), so the detail pass runs on
+    // the second stream beside it; the second stage's reconstruction, which
+    // overwrites the patches, waits for it.  Not with the kernel timers on.
+    const bool fork = g->aux && !g->prof.on;
+    if (fork) {
+      (void)hipEventRecord(g->ev_fork, g->stream);
+      (void)hipStreamWaitEvent(g->aux, g->ev_fork, 0);
+      details_pass(g, u, nullptr, nullptr, g->aux);
+      (void)hipEventRecord(g->ev_join, g->aux);
+    } else {
+      details_pass(g, u, nullptr, nullptr);
+    }
+    enqueue_rk3(g, field, dt, vd, true, fork ? g->ev_join : nullptr);
   });
   if (st != MR_OK) return st;
   const size_t n = g->leaves.size();
