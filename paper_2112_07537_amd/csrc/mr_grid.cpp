@@ -182,6 +182,9 @@ struct mr_grid {
   std::vector<DevBuf> fields, alts;
   DevBuf tmpA, tmpB;
   DevBuf d_lev, d_ijk, d_cmap, d_poff, d_patch, d_err, d_cbase, d_cstep;
+  // second patch buffer of the same layout, for the later stages of a fused
+  // step while the detail pass still reads the first (allocated on demand)
+  DevBuf d_patch2;
   DevBuf d_bands, d_norms, d_icpar, d_mom;
   Lists stage, wide;
   Prof prof;
@@ -701,7 +704,7 @@ static mr_status commit_tree_impl(mr_grid* g) {
 }
 
 template <typename T>
-static DevGrid<T> view(mr_grid* g, void* field) {
+static DevGrid<T> view(mr_grid* g, void* field, void* patch = nullptr) {
   DevGrid<T> d{};
   d.nb = g->nb;
   d.nblk = int32_t(g->leaves.size());
@@ -712,7 +715,7 @@ static DevGrid<T> view(mr_grid* g, void* field) {
   d.cbase = static_cast<const int64_t*>(g->d_cbase.p);
   d.cstep = static_cast<const int32_t*>(g->d_cstep.p);
   d.field = static_cast<T*>(field);
-  d.patch = static_cast<T*>(g->d_patch.p);
+  d.patch = static_cast<T*>(patch ? patch : g->d_patch.p);
   d.dw = g->Dw;
   d.err = static_cast<int32_t*>(g->d_err.p);
   return d;
@@ -721,13 +724,13 @@ static DevGrid<T> view(mr_grid* g, void* field) {
 struct AnyView {
   alignas(16) unsigned char raw[sizeof(DevGrid<double>)];
 };
-static AnyView anyview(mr_grid* g, void* field) {
+static AnyView anyview(mr_grid* g, void* field, void* patch = nullptr) {
   AnyView v;
   if (g->f32) {
-    DevGrid<float> d = view<float>(g, field);
+    DevGrid<float> d = view<float>(g, field, patch);
     std::memcpy(v.raw, &d, sizeof(d));
   } else {
-    DevGrid<double> d = view<double>(g, field);
+    DevGrid<double> d = view<double>(g, field, patch);
     std::memcpy(v.raw, &d, sizeof(d));
   }
   return v;
@@ -760,8 +763,8 @@ static void prof_end(mr_grid* g, int fam, hipEvent_t a, hipEvent_t b, bool tight
 }
 
 // Ghost reconstruction of `field` at depth D (stage G or wide Dw).
-static void ghost_fill(mr_grid* g, void* field, Lists& L) {
-  AnyView v = anyview(g, field);
+static void ghost_fill(mr_grid* g, void* field, Lists& L, void* patch = nullptr) {
+  AnyView v = anyview(g, field, patch);
   const Wavelet w{g->N, g->Nt};
   const bool plain = g->cfg.exec_mode == 1;
   hipEvent_t a = nullptr, b = nullptr;
@@ -793,8 +796,8 @@ static void ghost_fill(mr_grid* g, void* field, Lists& L) {
 }
 
 static void rhs_stage(mr_grid* g, void* y, const void* un, void* out, double a_un, double b_y,
-                      double dt, const VelDev& vel) {
-  AnyView v = anyview(g, y);
+                      double dt, const VelDev& vel, void* patch = nullptr) {
+  AnyView v = anyview(g, y, patch);
   const int n = int(g->leaves.size());
   hipEvent_t a = nullptr, e = nullptr;
   const bool plain = g->cfg.exec_mode == 1;
@@ -1230,24 +1233,48 @@ static double usum(const mr_velocity& v) {
   return std::fabs(v.p[0]) + std::fabs(v.p[1]) + std::fabs(v.p[2]);
 }
 
-// One SSP-RK3 step.  With `filled`, the ghosts of the field are already
-// those of a wide reconstruction of its current values (a detail pass just
-// before): its patches hold every value of the stage depth, so the first
-// stage does not reconstruct them again.  `join`, if given, is an event the
-// second reconstruction must wait for: it overwrites the patches, which
-// work on another stream may still be reading.
-static void enqueue_rk3(mr_grid* g, int field, double dt, const VelDev& vd, bool filled = false,
-                        hipEvent_t join = nullptr) {
+// One SSP-RK3 step: each stage reconstructs the ghosts of its input, then
+// applies the RHS and the stage update.
+static void enqueue_rk3(mr_grid* g, int field, double dt, const VelDev& vd) {
   void* u = g->fields[field].p;
   void* A = g->tmpA.p;
   void* B = g->tmpB.p;
-  if (!filled) ghost_fill(g, u, g->stage);
+  ghost_fill(g, u, g->stage);
   rhs_stage(g, u, u, A, 0.0, 1.0, dt, vd);
-  if (join) (void)hipStreamWaitEvent(g->stream, join, 0);
   ghost_fill(g, A, g->stage);
   rhs_stage(g, A, u, B, 0.75, 0.25, dt, vd);
   ghost_fill(g, B, g->stage);
   rhs_stage(g, B, u, u, 1.0 / 3.0, 2.0 / 3.0, dt, vd);
+}
+
+// Detail pass + RK3 step.  The wide reconstruction of the field serves both
+// the detail pass and the first stage (its patches hold every value of the
+// stage depth).  The detail pass reads only the field and those patches, so
+// it runs on the second stream while the step goes on: the later stages
+// reconstruct into the second patch buffer, and the last stage, which
+// overwrites the field, waits for the detail pass.  With the kernel timers
+// on, everything runs in order on the grid's stream.
+static void enqueue_fused(mr_grid* g, int field, double dt, const VelDev& vd) {
+  void* u = g->fields[field].p;
+  void* A = g->tmpA.p;
+  void* B = g->tmpB.p;
+  ghost_fill(g, u, g->wide);
+  const bool fork = g->aux && !g->prof.on && g->d_patch2.p;
+  void* p2 = fork ? g->d_patch2.p : nullptr;
+  if (fork) {
+    (void)hipEventRecord(g->ev_fork, g->stream);
+    (void)hipStreamWaitEvent(g->aux, g->ev_fork, 0);
+    details_pass(g, u, nullptr, nullptr, g->aux);
+    (void)hipEventRecord(g->ev_join, g->aux);
+  } else {
+    details_pass(g, u, nullptr, nullptr);
+  }
+  rhs_stage(g, u, u, A, 0.0, 1.0, dt, vd);
+  ghost_fill(g, A, g->stage, p2);
+  rhs_stage(g, A, u, B, 0.75, 0.25, dt, vd, p2);
+  ghost_fill(g, B, g->stage, p2);
+  if (fork) (void)hipStreamWaitEvent(g->stream, g->ev_join, 0);
+  rhs_stage(g, B, u, u, 1.0 / 3.0, 2.0 / 3.0, dt, vd, p2);
 }
 
 static mr_status check_step_args(mr_grid* g, int32_t field, double dt, const mr_velocity* vel,
@@ -1302,7 +1329,7 @@ static void free_grid(mr_grid* g) {
   DevBuf* bufs[] = {&g->tmpA, &g->tmpB, &g->d_lev, &g->d_ijk, &g->d_cmap, &g->d_poff, &g->d_patch,
                     &g->d_err, &g->d_bands, &g->d_norms, &g->d_icpar, &g->d_mom,
                     &g->stage.dg, &g->stage.dr, &g->wide.dg, &g->wide.dr, &g->ad_pairs,
-                    &g->d_cbase, &g->d_cstep,
+                    &g->d_cbase, &g->d_cstep, &g->d_patch2,
                     &g->ad_items, &g->ad_scr, &g->ad_det, &g->ad_slot};
   for (DevBuf* b : bufs) b->release();
   if (g->aux) {
@@ -1571,24 +1598,10 @@ mr_status mr_details_rk3_step(mr_grid* g, int32_t field, double dt, const mr_vel
   mr_status st = check_step_args(g, field, dt, vel, vd);
   if (st != MR_OK) return st;
   if (!norms && !on_device) return fail(MR_EINVAL, "bad argument");
-  st = run_step(g, g->fused_graph, field, dt, vel, [&] {
-    void* u = g->fields[field].p;
-    ghost_fill(g, u, g->wide);
-    // The detail pass and the first stage's RHS both only read the field and
-    // its patches (and write disjoint buffers), so the detail pass runs on
-    // the second stream beside it; the second stage's reconstruction, which
-    // overwrites the patches, waits for it.  Not with the kernel timers on.
-    const bool fork = g->aux && !g->prof.on;
-    if (fork) {
-      (void)hipEventRecord(g->ev_fork, g->stream);
-      (void)hipStreamWaitEvent(g->aux, g->ev_fork, 0);
-      details_pass(g, u, nullptr, nullptr, g->aux);
-      (void)hipEventRecord(g->ev_join, g->aux);
-    } else {
-      details_pass(g, u, nullptr, nullptr);
-    }
-    enqueue_rk3(g, field, dt, vd, true, fork ? g->ev_join : nullptr);
-  });
+  // the second patch buffer is allocated outside any graph capture
+  if (g->aux && !g->prof.on)
+    HIPCHK(g->d_patch2.ensure(std::max<int64_t>(1, g->patch_elems) * g->esz));
+  st = run_step(g, g->fused_graph, field, dt, vel, [&] { enqueue_fused(g, field, dt, vd); });
   if (st != MR_OK) return st;
   const size_t n = g->leaves.size();
   if (on_device) {
