@@ -176,7 +176,11 @@ mr_status mr_rk3_step(mr_grid* g, int32_t field, double dt, const mr_velocity* v
  * norms, on_device: as in mr_details; with on_device = 0 the call
  * synchronises, and MR_ENONFINITE is returned after the step has been
  * applied.  Asynchronous with on_device = 1; captured into a graph of its
- * own in graph execution mode. */
+ * own in graph execution mode.  The detail pass runs on a second,
+ * library-owned stream beside the step and is joined back into the grid's
+ * stream before the call's work ends there.  The first call (and the first
+ * after a tree grows) allocates a second ghost-patch buffer of the same size
+ * as the first; it is freed by mr_grid_destroy. */
 mr_status mr_details_rk3_step(mr_grid* g, int32_t field, double dt, const mr_velocity* vel,
                               double* norms, int32_t on_device);
 
