@@ -61,7 +61,7 @@ CASES = [(16, 4, 2, 4, "f64"), (16, 2, 0, 4, "f64"), (24, 6, 2, 6, "f32"), (24, 
 
 
 @pytest.mark.parametrize("nb,N,Nt,fd,prec", CASES)
-@pytest.mark.parametrize("exec_mode", [0, 2])
+@pytest.mark.parametrize("exec_mode", [0, 1, 2])
 def test_fused_equals_details_then_step(nb, N, Nt, fd, prec, exec_mode):
     vel = mr.velocity("shear")
     a = grid(nb, N, Nt, fd, prec, exec_mode)
