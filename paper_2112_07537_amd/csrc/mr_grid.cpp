@@ -121,6 +121,9 @@ struct Lists {
   std::vector<GItem> g;
   std::vector<RItem> r;
   int lds_g = 0;
+  // c->f launch groups [gb[i], gb[i+1]): substitution items one level at a
+  // time, finest first, then every patch item (READING R-ORDER)
+  std::vector<int> gb;
   // f->c items grouped by pass-1 column length (extent along y or z):
   // classes <= 3, <= 6, <= 12 at [rcls[c], rcls[c+1]) with their LDS sizes
   int rcls[4] = {0, 0, 0, 0};
@@ -599,6 +602,24 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
   L.lds_g = 0;
   for (const GItem& it : L.g) L.lds_g = std::max(L.lds_g, gview_lds(it, N, esz));
   {
+    // Launch order (READING R-ORDER).  A substitution reads the level-(L-1)
+    // points around its slab, which in a coarser neighbour are all of that
+    // neighbour's points; the neighbour's own substitution may rewrite some
+    // of them.  Substitutions therefore run one level at a time, finest
+    // first, so each reads the values from before any substitution.  c->f
+    // patches read substituted values, so they run after all of them.  Block
+    // order is kept inside each group.
+    auto key = [&](const GItem& it) {
+      return (it.sel & 16) ? 64 - g->leaves[it.blk].L : 128;
+    };
+    std::stable_sort(L.g.begin(), L.g.end(),
+                     [&](const GItem& a, const GItem& b) { return key(a) < key(b); });
+    L.gb.assign(1, 0);
+    for (size_t i = 1; i < L.g.size(); ++i)
+      if (key(L.g[i]) != key(L.g[i - 1])) L.gb.push_back(int(i));
+    if (!L.g.empty()) L.gb.push_back(int(L.g.size()));
+  }
+  {
     auto cls = [](const RItem& it) {
       const int q = std::min(it.hi[1] - it.lo[1], it.hi[2] - it.lo[2]);
       return q <= 3 ? 0 : (q <= 6 ? 1 : (q <= 12 ? 2 : 3));
@@ -768,13 +789,16 @@ static void ghost_fill(mr_grid* g, void* field, Lists& L, void* patch = nullptr)
   const Wavelet w{g->N, g->Nt};
   const bool plain = g->cfg.exec_mode == 1;
   hipEvent_t a = nullptr, b = nullptr;
-  if (!L.g.empty()) {
+  // substitution one level at a time (finest first), then the c->f patches;
+  // each group is one launch, timed on its own
+  const GItem* gi = static_cast<const GItem*>(L.dg.p);
+  for (size_t k = 0; k + 1 < L.gb.size(); ++k) {
+    const int i0 = L.gb[k], i1 = L.gb[k + 1];
     prof_begin(g, 2, &a, &b, !plain);
     if (plain) {
-      for (size_t i = 0; i < L.g.size(); ++i)
-        launch_gview(g->f32, v.raw, w, static_cast<const GItem*>(L.dg.p) + i, 1, L.lds_g, g->stream);
+      for (int i = i0; i < i1; ++i) launch_gview(g->f32, v.raw, w, gi + i, 1, L.lds_g, g->stream);
     } else {
-      launch_gview(g->f32, v.raw, w, static_cast<const GItem*>(L.dg.p), int(L.g.size()), L.lds_g, g->stream);
+      launch_gview(g->f32, v.raw, w, gi + i0, i1 - i0, L.lds_g, g->stream);
     }
     prof_end(g, 2, a, b, !plain, L.out_points);
   }

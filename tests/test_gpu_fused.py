@@ -138,3 +138,24 @@ def test_fused_rejects_bad_arguments():
         g.details_rk3_step(-1.0, mr.velocity("shear"))
     assert e.value.code == mr.MR_EINVAL
     g.close()
+
+
+def test_fused_async_matches_sync():
+    """The asynchronous form (norms left on the device, no synchronisation)
+    does the same work as the synchronous one.  Batched ghost launches are
+    reproducible to about 1e-15 of max|phi| run to run, not bit for bit, so
+    the comparison takes the parity tolerance."""
+    vel = mr.velocity("shear")
+    a = grid(24, 6, 2, 6, "f32")
+    b = grid(24, 6, 2, 6, "f32")
+    dt = a.cfl_dt(vel, 0.5)
+    scale = np.abs(a.field_get()).max()
+    for _ in range(2):
+        a.details_rk3_step_async(dt, vel)
+        b.details_rk3_step(dt, vel)
+    a.sync()
+    tol = TOL["f32"] * scale
+    assert np.abs(a.field_get().astype(np.float64) - b.field_get()).max() <= tol
+    assert np.abs(a.details() - b.details()).max() <= tol
+    a.close()
+    b.close()
