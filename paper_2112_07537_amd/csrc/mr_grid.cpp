@@ -437,6 +437,31 @@ static void push_tiled(std::vector<Item>& out, Item it, F lds_of, int kLdsBudget
 
 static int Hreach(int N, int Nt) { return Nt ? N : 0; }
 
+// Box a minus box b as disjoint boxes, appended to out (other fields of a).
+static void box_subtract(const GItem& a, const GItem& b, std::vector<GItem>& out) {
+  for (int c = 0; c < 3; ++c)
+    if (a.hi[c] <= b.lo[c] || b.hi[c] <= a.lo[c]) {
+      out.push_back(a);
+      return;
+    }
+  GItem rest = a;
+  for (int c = 0; c < 3; ++c) {
+    if (rest.lo[c] < b.lo[c]) {
+      GItem p = rest;
+      p.hi[c] = b.lo[c];
+      out.push_back(p);
+      rest.lo[c] = b.lo[c];
+    }
+    if (rest.hi[c] > b.hi[c]) {
+      GItem p = rest;
+      p.lo[c] = b.hi[c];
+      out.push_back(p);
+      rest.hi[c] = b.hi[c];
+    }
+  }
+  // what is left of a lies inside b
+}
+
 // Work lists of one ghost reconstruction at depth D: substitution slabs and
 // c->f patches (one launch), then f->c restrictions by the fine blocks (a
 // second launch, which reads the fine blocks' substituted values and their
@@ -464,6 +489,7 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
   };
   auto one_block = [&](int b, Part& P) -> bool {
     const int Lb = g->leaves[b].L;
+    std::vector<GItem> slabs;   // lifted wavelets: made disjoint below
     for (int r = 0; r < 27; ++r) {
       if (r == 13) continue;
       const int lr = region_level(g, b, r);
@@ -504,7 +530,10 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
           for (int a = 0; a < 3; ++a, mul *= 3) r2 += mul * ((sub >> a) & 1 ? rr[a] : 1);
           if (region_level(g, b, r2) < Lb) covered = true;
         }
-        if (!sempty && !covered) push_tiled(P.g, sb, glds, kLdsBudgetRefine);
+        if (!sempty && !covered) {
+          if (Nt) slabs.push_back(sb);
+          else push_tiled(P.g, sb, glds, kLdsBudgetRefine);
+        }
       } else {
         // f->c: each finer leaf covering this region restricts its part
         region_box(nb, D, r, blo, bhi);
@@ -572,7 +601,24 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
         }
         push_tiled(P.g, pt, glds, kLdsBudgetRefine);
       }
-      return true;
+    // With lifting every slab takes the same points (at least one odd index),
+    // so overlapping slabs (two faces meet along an edge) can be cut into
+    // disjoint boxes: each point is then written by exactly one item, and
+    // the result does not depend on which of two items writes last.
+    if (!slabs.empty()) {
+      std::vector<GItem> acc, pieces, next;
+      for (const GItem& sl : slabs) {
+        pieces.assign(1, sl);
+        for (const GItem& q : acc) {
+          next.clear();
+          for (const GItem& pc : pieces) box_subtract(pc, q, next);
+          pieces.swap(next);
+        }
+        acc.insert(acc.end(), pieces.begin(), pieces.end());
+      }
+      for (const GItem& pc : acc) push_tiled(P.g, pc, glds, kLdsBudgetRefine);
+    }
+    return true;
   };
   const int nchunk = std::max(1, std::min(64, n / 256));
   std::vector<Part> parts(nchunk);
