@@ -120,9 +120,12 @@ def cpu_baseline(g, cfg, n_sample=400, seed=1234, budget_s=15.0):
     t0 = time.perf_counter()
     done = 0
     for k in sample:
+        mask = o.substitution_mask(k)
         for _ in range(3):
-            for key, z, y, x, v in o.substitution_writes(k):
-                o.blocks[key][z, y, x] = v
+            if mask.any():
+                for deg in (1, 2, 3):
+                    z, y, x, v = o.substitution_values(k, deg, mask)
+                    o.blocks[k][z, y, x] = v
             o.rhs_block(k, vel)
         o.block_details(k)
         done += 1

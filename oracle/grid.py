@@ -20,7 +20,10 @@ at a level-L grid point P, which is what the ghost reconstruction of section
   * leaf holding P is coarser            -> G_L(P), the zero-detail refinement
     (coarse-extension assumption, section 2.2.2) of the level-(L-1) samples,
     each sample being the value of the leaf holding that coarse point
-    (the "Sample" of Part 1; injection when that leaf is finer);
+    (the "Sample" of Part 1; injection when that leaf is finer).  READING
+    R-ORDER: the samples are the values from before the substitution of the
+    current reconstruction (Part 1 refines the coarse data before Part 2
+    overwrites anything);
   * leaf holding P is finer (one level)  -> [H^a x H^a x H^a] restriction of
     Phi_{L+1} (coarsening of the fine data incl. its ghosts, Part 2);
     inside that restriction, points held by an even finer leaf are injected
@@ -74,8 +77,19 @@ class Grid:
         self.level_min, self.level_max = level_min, level_max
         self.eps_r, self.eps_c = eps_refine, eps_coarsen
         self.detail_ext = detail_ext
+        self._pre = None          # field before the last substitution (R-ORDER)
         self.blocks = {}          # (L, i, j, k) -> float64 array [z, y, x]
         self._index()
+
+    @property
+    def blocks(self):
+        return self._blocks
+
+    @blocks.setter
+    def blocks(self, value):
+        # a new field: the samples of G_L are read from it again
+        self._blocks = value
+        self._pre = None
 
     # ------------------------------------------------------------------ tree
     def _index(self):
@@ -123,9 +137,11 @@ class Grid:
         assert (lev >= 0).all(), "point outside every leaf"
         return lev
 
-    def values_at(self, l, L, X, Y, Z):
+    def values_at(self, l, L, X, Y, Z, src=None):
         """Values of the level-l leaves at level-L points P (l >= L, or P on
-        the level-l grid).  P must lie in level-l leaves."""
+        the level-l grid).  P must lie in level-l leaves.  ``src`` is the
+        block dict read (default: the current field)."""
+        src = self.blocks if src is None else src
         W = self.width(L)
         X, Y, Z = X % W, Y % W, Z % W
         if l >= L:
@@ -144,7 +160,7 @@ class Grid:
             m = code == c
             key = (l, int(c & ((1 << 21) - 1)), int((c >> 21) & ((1 << 21) - 1)),
                    int(c >> 42))
-            a = self.blocks[key]
+            a = src[key]
             out[m] = a[Zl[m] % nb, Yl[m] % nb, Xl[m] % nb]
         return out
 
@@ -159,14 +175,18 @@ class Grid:
     def sample_box(self, L, lo, shape):
         """Level-L samples used as coarse data by a refinement (Part 1
         "Sample"): the value of the leaf holding each point, by injection when
-        that leaf is at level L or finer; G_L when it is coarser."""
+        that leaf is at level L or finer; G_L when it is coarser.  Values are
+        those from before the last substitution (READING R-ORDER); the
+        substitution never changes a point that a finer level samples (it
+        keeps every all-even point), so only coarser leaves' values differ."""
         X, Y, Z = self._box(lo, shape)
         lev = self.owner_level(L, X, Y, Z)
         out = np.empty(X.shape)
+        src = self._pre if self._pre is not None else self.blocks
         for l in np.unique(lev):
             m = lev == l
             if l >= L:
-                out[m] = self.values_at(int(l), L, X[m], Y[m], Z[m])
+                out[m] = self.values_at(int(l), L, X[m], Y[m], Z[m], src)
         if (lev < L).any():
             G = self.refine_box(L, lo, shape)
             out[lev < L] = G[lev < L]
@@ -253,65 +273,112 @@ class Grid:
 
     # --------------------------------------------------------- substitution
     def substitution_slab(self, d):
-        """READING R-SUB: slab of a fine block next to a coarser leaf in
-        direction d whose neglected details are overwritten (section 2.2.4 and
-        section 2.3).  Returns per-axis ranges and a selector on points."""
+        """READING R-SUB: per-axis ranges [lo, hi) of the slab of a fine block
+        next to a coarser leaf in direction d (sections 2.2.2, 2.2.4, 2.3).
+        The slab holds the points whose details the zero-detail ghost
+        refinement takes as zero: lifted, the details around every even
+        sample of the fine block that the refinement of its ghost points reads
+        (N-1 points in front, N-2 behind) enter those samples through the
+        lifting; unlifted, only the tangential details at those samples enter
+        (the 3D inverse transform reads them along the facing axis).  Seen
+        from the neighbour that would coarsen, the far end of the slab lies at
+        the distance of the 3D "coarse region extension" column of Table 3."""
         N, nb = self.N, self.nb
         rng = []
         for a in range(3):
             if d[a] == 0:
                 rng.append((0, nb))
             elif self.Nt == 0:
-                rng.append((0, N - 1) if d[a] < 0 else (nb - N + 2, nb - 1))
+                rng.append((0, N - 1) if d[a] < 0 else (nb - N + 2, nb))
             else:
                 rng.append((0, N) if d[a] < 0 else (nb - N + 1, nb))
         return rng
 
-    def substitution_writes(self, key):
-        """Points of block ``key`` overwritten by the substitution step of
-        section 2.2.4 / 2.3 (see ``substitute``) and their new values."""
+    def substitution_mask(self, key):
+        """Points of block ``key`` whose neglected details are discarded: the
+        union, over the directions with a coarser leaf, of the R-SUB slab
+        points taken by the selector (lifted: every point with an odd index;
+        unlifted: even on the facing axes and odd on a tangential axis)."""
+        nb = self.nb
         L = key[0]
-        writes = []
+        z, y, x = np.meshgrid(np.arange(nb), np.arange(nb), np.arange(nb), indexing="ij")
+        pos = (x, y, z)
+        M = np.zeros((nb, nb, nb), bool)
         for d in DIRS:
             if self.neighbor_level(key, d) >= L:
                 continue
             rng = self.substitution_slab(d)
-            lo = np.array([r[0] for r in rng])
-            shape = np.array([r[1] - r[0] for r in rng])
-            if (shape <= 0).any():
-                continue
-            G = self.refine_box(L, self.origin(key) + lo, shape)
-            x, y, z = self._box(lo, shape)
-            par = [x % 2, y % 2, z % 2]
+            inr = np.ones((nb, nb, nb), bool)
+            for a in range(3):
+                inr &= (pos[a] >= rng[a][0]) & (pos[a] < rng[a][1])
             if self.Nt > 0:
-                sel = (par[0] + par[1] + par[2]) > 0
+                take = (x % 2 + y % 2 + z % 2) > 0
             else:
-                sel = np.ones(x.shape, bool)
-                tang_odd = np.zeros(x.shape, bool)
+                take = np.ones((nb, nb, nb), bool)
+                tang_odd = np.zeros((nb, nb, nb), bool)
                 for a in range(3):
                     if d[a] != 0:
-                        sel &= par[a] == 0
+                        take &= pos[a] % 2 == 0
                     else:
-                        tang_odd |= par[a] == 1
-                sel &= tang_odd
-            if sel.any():
-                writes.append((key, z[sel], y[sel], x[sel], G[sel]))
-        return writes
+                        tang_odd |= pos[a] % 2 == 1
+                take &= tang_odd
+            M |= inr & take
+        return M
+
+    def substitution_values(self, key, deg, M):
+        """Substitution of section 2.3 for the points of degree ``deg`` (number
+        of odd indices) in the mask M of block ``key``: each gets the value
+        that makes its detail vanish, minus the sum over the non-central taps
+        of the tensor product of G^a over its odd axes (the G^a centre tap is
+        1; READING: the 1D sign of section 2.2.4).  The taps read the block's
+        level view at depth N-1 as it stands, so degree-1 points read only
+        all-even points and degree 2 and 3 read the values of the lower
+        degrees set before them.  Returns (z, y, x, values)."""
+        N = self.N
+        D = N - 1
+        X = self.ghost_block(key, D)
+        ga = wv.table(N, 0)["Ga"]
+        z, y, x = np.nonzero(M)
+        par = (x % 2, y % 2, z % 2)
+        keep = (par[0] + par[1] + par[2]) == deg
+        z, y, x = z[keep], y[keep], x[keep]
+        par = (x % 2, y % 2, z % 2)
+        out = np.zeros(len(x))
+        for pat in {(a, b, c) for a, b, c in zip(*par)}:
+            sel = (par[0] == pat[0]) & (par[1] == pat[1]) & (par[2] == pat[2])
+            taps = [ga if pat[a] else {0: 1.0} for a in range(3)]
+            acc = np.zeros(int(sel.sum()))
+            for oz in sorted(taps[2]):
+                for oy in sorted(taps[1]):
+                    for ox in sorted(taps[0]):
+                        if (ox, oy, oz) == (0, 0, 0):
+                            continue
+                        w = taps[2][oz] * taps[1][oy] * taps[0][ox]
+                        acc = acc + w * X[z[sel] + D + oz, y[sel] + D + oy, x[sel] + D + ox]
+            out[sel] = -acc
+        return z, y, x, out
 
     def substitute(self):
-        """Substitution step of section 2.2.4 / 2.3 on every fine block next to
-        a coarser leaf: each selected point gets the tensor-product
-        Deslauriers-Dubuc prediction over its odd axes from the even (0-degree)
-        points around it -- i.e. G_L, which zeroes the neglected detail of
-        degree 1, 2 and 3 in that order.  Only points with an odd index are
-        written and only 0-degree points are read, so the result does not
-        depend on the order in which blocks or slabs are visited."""
-        writes = []
-        for key in sorted(self.blocks):
-            writes += self.substitution_writes(key)
-        for key, z, y, x, v in writes:
-            self.blocks[key][z, y, x] = v
-        return len(writes)
+        """Substitution step of sections 2.2.4 and 2.3 on every fine block
+        next to a coarser leaf, in degree order: all degree-1 points of every
+        block, then degree 2, then degree 3 (each degree reads the values the
+        lower degrees were given, in its own block and in its same-level
+        neighbours; ghost values in coarser regions come from the samples
+        before the substitution, READING R-ORDER).  Returns the number of
+        points written."""
+        pre = {k: v.copy() for k, v in self.blocks.items()}
+        masks = {k: self.substitution_mask(k) for k in sorted(self.blocks)}
+        self._pre = pre
+        n = 0
+        for deg in (1, 2, 3):
+            writes = []
+            for key, M in masks.items():
+                if M.any():
+                    writes.append((key,) + self.substitution_values(key, deg, M))
+            for key, z, y, x, v in writes:
+                self._blocks[key][z, y, x] = v
+                n += len(v)
+        return n
 
     # ---------------------------------------------------------------- RHS
     def positions(self, key):
@@ -692,6 +759,7 @@ class Grid:
         return self.adapt()
 
     def sample(self, ic):
+        self._pre = None
         for key in self.blocks:
             x, y, z = self.positions(key)
             Z, Y, X = np.meshgrid(z, y, x, indexing="ij")

@@ -144,3 +144,38 @@ def synthesis_global(u, N, Nt):
         r[1::2] = odd
         out = np.moveaxis(r, 0, axis)
     return out
+
+
+def level_field(tl, N):
+    """Global level-Lf field of a two-level tree: the fine leaves' values
+    where a fine leaf holds the point, the refinement G elsewhere."""
+    return np.where(tl.fine_mask, tl.fine, tl.refined(N))
+
+
+def point_details(f, N):
+    """Detail of every point of a periodic level field with respect to the
+    interpolating prediction, over the point's odd axes only: along x, then
+    y, then z, odd positions take value minus the Lagrange prediction from
+    the even positions of the running array (the all-even points keep their
+    value).  Degree-k points thus get the tensor product of the k 1D
+    predict-and-subtract filters, the quantity the substitution zeroes."""
+    w = lagrange_midpoint_weights(N)
+    out = f.copy()
+    for axis in (2, 1, 0):
+        a = np.moveaxis(out, axis, 0)
+        ev = a[0::2]
+        pred = np.zeros(ev.shape)
+        for j in sorted(w):
+            pred = pred + float(w[j]) * np.roll(ev, -j, axis=0)
+        r = a.copy()
+        r[1::2] = a[1::2] - pred
+        out = np.moveaxis(r, 0, axis)
+    return out
+
+
+def lifted_coarse(f, N, Nt):
+    """Level-(Lf-1) scaling coefficients [H^a]^3 f of a periodic level field."""
+    out = f
+    for ax in (2, 1, 0):
+        out = restrict_axis(out, ax, N, Nt)
+    return out

@@ -1,8 +1,9 @@
 """Pins of the block-octree oracle against what the paper and mathematics fix.
 
 * Brute force on tiny two-level trees (independent global formulation in
-  tests/brute.py): c->f ghosts and substituted points equal the global
-  Deslauriers-Dubuc refinement; f->c ghosts equal the global restriction.
+  tests/brute.py): c->f ghosts equal the global Deslauriers-Dubuc
+  refinement; f->c ghosts equal the global restriction.  The substitution
+  has its own pins in test_oracle_substitution.py.
 * Polynomial exactness of ghosts, substitution and details (sections 2.1.3,
   2.2.2 and 2.2.4): per-axis degree < N is reproduced exactly.
 * One RK3 step on a uniform periodic grid equals the Fourier closed form
@@ -58,20 +59,18 @@ def test_brute_force_two_level(N, Nt):
     keys = two_level_tree(nb, 1, lambda i, j, k: (i, j, k) in ((0, 0, 0), (1, 1, 0), (0, 1, 1)))
     g.set_tree(keys, init=rough_field(11 + N + Nt))
     orig = {k: v.copy() for k, v in g.blocks.items()}
-    bf = brute.TwoLevel(nb, 2, orig)
+    g.substitute()
+    # the substitution changes no all-even point, so the global refinement of
+    # the samples is the same before and after it
+    bf = brute.TwoLevel(nb, 2, {k: v.copy() for k, v in g.blocks.items()})
     G = bf.refined(N)
     W = nb << 2
-    g.substitute()
     changed = 0
     for key in g.keys():
         if key[0] != 2:
             continue
         o = g.origin(key)
-        sl = (slice(o[2], o[2] + nb), slice(o[1], o[1] + nb), slice(o[0], o[0] + nb))
-        diff = g.blocks[key] != orig[key]
-        changed += int(diff.sum())
-        # every substituted point equals the global refinement
-        np.testing.assert_allclose(g.blocks[key][diff], G[sl][diff], rtol=0, atol=1e-13)
+        changed += int((g.blocks[key] != orig[key]).sum())
         # c->f ghosts (points in coarser leaves) equal G
         D = 4
         X = g.ghost_block(key, D)
@@ -102,38 +101,6 @@ def test_brute_force_two_level(N, Nt):
         lev = g.owner_level(1, xx, yy, zz)
         m = lev == 2
         np.testing.assert_allclose(X[m], C[zz[m], yy[m], xx[m]], rtol=0, atol=1e-12)
-
-
-@pytest.mark.parametrize("N,Nt", ALL_WAVELETS)
-def test_substitution_slab_matches_refinement(N, Nt):
-    """After substitution, every point of the R-SUB slab of a fine block facing
-    a coarser face neighbour equals the global refinement G."""
-    nb = 16
-    g = og.Grid(nb, N, Nt)
-    keys = two_level_tree(nb, 1, lambda i, j, k: (i, j, k) == (0, 0, 0))
-    g.set_tree(keys, init=rough_field(5))
-    bf = brute.TwoLevel(nb, 2, {k: v.copy() for k, v in g.blocks.items()})
-    G = bf.refined(N)
-    g.substitute()
-    count = 0
-    # (2,1,0,0) faces the coarse (1,1,0,0) across +x; (2,0,0,0) faces it
-    # across -x through the periodic wrap
-    for key, side in (((2, 1, 0, 0), +1), ((2, 0, 0, 0), -1)):
-        a = g.blocks[key]
-        o = g.origin(key)
-        if Nt == 2:
-            xs = range(nb - N + 1, nb) if side > 0 else range(0, N)
-            sel = lambda x, y, z: (x % 2) + (y % 2) + (z % 2) > 0
-        else:
-            xs = range(nb - N + 2, nb - 1, 2) if side > 0 else range(0, N - 1, 2)
-            sel = lambda x, y, z: (y % 2) + (z % 2) > 0
-        for x in xs:
-            for y in range(nb):
-                for z in range(nb):
-                    if sel(x, y, z):
-                        assert abs(a[z, y, x] - G[o[2] + z, o[1] + y, o[0] + x]) < 1e-13
-                        count += 1
-    assert count > 0
 
 
 # ------------------------------------------------------ polynomial exactness

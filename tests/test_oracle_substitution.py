@@ -1,0 +1,346 @@
+"""Pins of the oracle's substitution step (sections 2.2.2, 2.2.4, 2.3) and of
+its detail-band reading (section 2.2.5), against the paper and against an
+independent global formulation (tests/brute.py).
+
+* Extent: on a line where only one face slab applies, the farthest point the
+  substitution changes lies at the distance that the 3D "coarse region
+  extension" column of Table 3 (tests/golden/ghost_point_requirements.txt)
+  gives, seen from the neighbour that would coarsen; the nearest is on the
+  block boundary.
+* 1D reduction: with data that varies along x only, 2.2 changes exactly the
+  first and the last odd point of a fine block between two coarse regions
+  (the details gamma_2^0 and gamma_4^0 of the 1D sketches of section 2.2.2),
+  every lifted wavelet changes the odd points within the 1D column of Table 3,
+  and no unlifted wavelet changes anything (1D column "0").
+* Formula (section 2.3): after the substitution the detail of every changed
+  point, over its odd axes, is zero in the final field.
+* Consistency of the coarse-extension assumption (section 2.2.2): after the
+  substitution, the global level-L field (fine leaves' values, refinement
+  elsewhere) has no detail at any point of a coarser leaf, and, lifted, the
+  [H^a]^3 coarse coefficient of every fine-leaf sample that the refinement
+  reads equals that sample (so the slab is large enough).  Leaving out the
+  farthest slab point breaks one of these (so it cannot end earlier).
+* Detail band (READING R-EXT): a detail planted in a same-level neighbour at
+  the band's distance enters a block's norm, one point farther does not, and
+  neither does a detail on the neighbour's far side or in a coarser or finer
+  neighbour.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import grid as og
+from oracle import wavelets as wv
+from tests import brute
+
+WAVELETS = wv.WAVELETS
+NB = 16
+HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _table3():
+    out = {}
+    with open(os.path.join(HERE, "ghost_point_requirements.txt")) as f:
+        for ln in f:
+            if ln.strip() and not ln.startswith("#"):
+                v = [int(x) for x in ln.split()]
+                out[(v[0], v[1])] = dict(ef1=v[4], ef3=v[5], eb1=v[6], eb3=v[7])
+    return out
+
+
+TABLE3 = _table3()
+
+
+def octant_tree(nb):
+    """Level-1 tree with octant (0,0,0) refined: fine block (2,0,0,0) has the
+    coarse leaf (1,1,0,0) across its -x face (periodic wrap), fine block
+    (2,1,0,0) has it across its +x face."""
+    keys = []
+    for k in range(2):
+        for j in range(2):
+            for i in range(2):
+                if (i, j, k) == (0, 0, 0):
+                    keys += [(2, c & 1, (c >> 1) & 1, (c >> 2) & 1) for c in range(8)]
+                else:
+                    keys.append((1, i, j, k))
+    return keys
+
+
+def rough(seed, nb=NB):
+    rng = np.random.default_rng(seed)
+    return lambda key: rng.standard_normal((nb, nb, nb))
+
+
+def changed_x(before, after, y, z):
+    return sorted(int(x) for x in np.nonzero(before[z, y, :] != after[z, y, :])[0])
+
+
+@pytest.mark.parametrize("N,Nt", WAVELETS)
+def test_extent_is_table3_extension(N, Nt):
+    g = og.Grid(NB, N, Nt)
+    g.set_tree(octant_tree(NB), init=rough(3 + N + Nt))
+    before = {k: v.copy() for k, v in g.blocks.items()}
+    g.substitute()
+    t = TABLE3[(N, Nt)]
+    # middle lines (no y or z slab reaches them); y odd so that the unlifted
+    # selector takes the line's points too
+    y, z = NB // 2 + 1, NB // 2
+    front = changed_x(before[(2, 0, 0, 0)], g.blocks[(2, 0, 0, 0)], y, z)
+    back = changed_x(before[(2, 1, 0, 0)], g.blocks[(2, 1, 0, 0)], y, z)
+    # the coarse neighbour of (2,0,0,0) sits in front of it: the block's slab
+    # is behind that neighbour, whose back extension is eb3
+    if t["eb3"] == 0:
+        assert front == []
+    else:
+        assert front[0] == 0 and front[-1] == t["eb3"] - 1, front
+    if t["ef3"] == 0:
+        assert back == []
+    else:
+        assert back[0] == NB - t["ef3"], back
+        assert back[-1] in (NB - 1, NB - 2), back   # unlifted: even points only
+
+
+@pytest.mark.parametrize("N,Nt", WAVELETS)
+def test_one_dimensional_reduction(N, Nt):
+    """Data varying along x only, fine blocks between coarse regions along x."""
+    nb = NB
+    keys = []
+    # level-1 tree, blocks with i = 0 refined: every fine block has coarse
+    # leaves in front and behind along x (periodic), fine ones along y and z
+    for k in range(2):
+        for j in range(2):
+            for i in range(2):
+                if i == 0:
+                    keys += [(2, c & 1, 2 * j + ((c >> 1) & 1), 2 * k + ((c >> 2) & 1))
+                             for c in range(8)]
+                else:
+                    keys.append((1, i, j, k))
+    rng = np.random.default_rng(7 + N + Nt)
+    f1 = rng.standard_normal(nb << 2)       # global fine x samples
+
+    def init(key):
+        L, i, j, k = key
+        s = 1 << (2 - L)
+        xs = f1[(i * nb + np.arange(nb)) * s]
+        return np.broadcast_to(xs, (nb, nb, nb)).copy()
+    g = og.Grid(nb, N, Nt)
+    g.set_tree(keys, init=init)
+    before = {k: v.copy() for k, v in g.blocks.items()}
+    g.substitute()
+    t = TABLE3[(N, Nt)]
+    if Nt == 2:
+        exp_front = list(range(1, t["eb1"], 2))
+        exp_back = list(range(nb - t["ef1"], nb, 2))
+    else:
+        exp_front, exp_back = [], []
+    for key in g.keys():
+        if key[0] != 2:
+            continue
+        # changed beyond rounding (the sums of the substitution round
+        # differently from the original values of points whose detail is 0)
+        ch = np.abs(g.blocks[key] - before[key]) > 1e-12
+        d = np.nonzero(ch.any(axis=(0, 1)))[0].tolist()
+        # fine block i = 0 has the coarse region in front (wrap), i = 1 behind
+        exp = exp_front if key[1] == 0 else exp_back
+        assert d == exp, (key, d, exp)
+        # every line changes alike
+        assert (ch == ch[:1, :1, :]).all()
+    if (N, Nt) == (2, 2):
+        # the paper's 1D sketch: gamma_2^0 sits on the first odd point of
+        # the fine region, gamma_4^0 on its last point
+        assert exp_front == [1] and exp_back == [nb - 1]
+
+
+def _final_field(g, N):
+    tl = brute.TwoLevel(g.nb, 2, {k: v.copy() for k, v in g.blocks.items()})
+    return tl, brute.level_field(tl, N)
+
+
+def _sample_mask(tl, N):
+    """Fine-leaf all-even points read as samples by the refinement of some
+    point of a coarser leaf (within N-1 fine points along every axis)."""
+    cr = ~tl.fine_mask
+    near = cr.copy()
+    for ax in range(3):
+        acc = near.copy()
+        for s in range(1, N):
+            acc |= np.roll(near, s, axis=ax) | np.roll(near, -s, axis=ax)
+        near = acc
+    W = cr.shape[0]
+    ev = (np.arange(W) % 2 == 0)
+    even3 = ev[:, None, None] & ev[None, :, None] & ev[None, None, :]
+    return near & even3 & tl.fine_mask
+
+
+def _residuals(tl, f, N, Nt):
+    """(max detail on coarser leaves, max |[H^a]^3 f - sample| over the fine
+    samples the refinement reads)."""
+    d = brute.point_details(f, N)
+    W = f.shape[0]
+    par = np.arange(W) % 2
+    odd = (par[:, None, None] + par[None, :, None] + par[None, None, :]) > 0
+    ra = float(np.abs(d[~tl.fine_mask & odd]).max())
+    rc = 0.0
+    if Nt:
+        lam = brute.lifted_coarse(f, N, Nt)
+        m = _sample_mask(tl, N)
+        rc = float(np.abs(lam[m[0::2, 0::2, 0::2]] - f[m][...]).max()) if m.any() else 0.0
+    return ra, rc
+
+
+@pytest.mark.parametrize("N,Nt", WAVELETS)
+def test_substituted_points_have_no_detail(N, Nt):
+    g = og.Grid(NB, N, Nt)
+    keys = [k for k in octant_tree(NB)]
+    g.set_tree(keys, init=rough(21 + N + Nt))
+    before = {k: v.copy() for k, v in g.blocks.items()}
+    g.substitute()
+    tl, f = _final_field(g, N)
+    d = brute.point_details(f, N)
+    W = NB << 2
+    n = 0
+    for key in g.keys():
+        if key[0] != 2:
+            continue
+        o = g.origin(key)
+        ch = g.blocks[key] != before[key]
+        sel = g.substitution_mask(key)
+        assert not (ch & ~sel).any()     # nothing outside the slabs changes
+        sub = d[o[2]:o[2] + NB, o[1]:o[1] + NB, o[0]:o[0] + NB]
+        if sel.any():
+            assert np.abs(sub[sel]).max() < 1e-12
+        n += int(sel.sum())
+    assert n > 0 and W > 0
+
+
+@pytest.mark.parametrize("N,Nt", WAVELETS)
+def test_coarse_extension_holds_after_substitution(N, Nt):
+    g = og.Grid(NB, N, Nt)
+    g.set_tree(octant_tree(NB), init=rough(31 + N + Nt))
+    tl0, f0 = _final_field(g, N)
+    ra0, rc0 = _residuals(tl0, f0, N, Nt)
+    assert ra0 > 1e-3 or rc0 > 1e-3    # rough data breaks it before
+    g.substitute()
+    tl, f = _final_field(g, N)
+    ra, rc = _residuals(tl, f, N, Nt)
+    assert ra < 1e-12 and rc < 1e-12, (ra, rc)
+
+
+@pytest.mark.parametrize("N,Nt", WAVELETS)
+def test_farthest_slab_point_is_needed(N, Nt):
+    """With the farthest point of the -x slab of block (2,0,0,0) on one middle
+    line left out of the substitution, the coarse-extension identities fail
+    (random data): the slab cannot end one point earlier.  That it need not
+    reach farther is the sufficiency test above."""
+    t = TABLE3[(N, Nt)]
+    if t["eb3"] == 0:
+        pytest.skip("no slab on this side")
+    g = og.Grid(NB, N, Nt)
+    g.set_tree(octant_tree(NB), init=rough(41 + N + Nt))
+    y, z, x = NB // 2 + 1, NB // 2, t["eb3"] - 1
+    full = g.substitution_mask
+
+    def mask(key):
+        m = full(key)
+        if key == (2, 0, 0, 0):
+            assert m[z, y, x]
+            m[z, y, x] = False
+        return m
+    g.substitution_mask = mask
+    g.substitute()
+    tl, f = _final_field(g, N)
+    ra, rc = _residuals(tl, f, N, Nt)
+    assert max(ra, rc) > 1e-6, (ra, rc)
+
+
+@pytest.mark.parametrize("N,Nt", WAVELETS)
+def test_every_substituted_kind_is_needed(N, Nt):
+    """For every parity pattern that the -x slab of block (2,0,0,0) takes,
+    leaving out its farthest point on a middle line breaks the
+    coarse-extension identities: the selector takes no point that the
+    assumption does not need."""
+    y0 = z0 = NB // 2
+    lo, hi = og.Grid(NB, N, Nt).substitution_slab((-1, 0, 0))[0]
+    seen = 0
+    for pat in [(a, b, c) for c in (0, 1) for b in (0, 1) for a in (0, 1) if a + b + c]:
+        xs = [x for x in range(lo, hi) if x % 2 == pat[0]]
+        if not xs:
+            continue
+        x, y, z = xs[-1], y0 + pat[1], z0 + pat[2]
+        g = og.Grid(NB, N, Nt)
+        g.set_tree(octant_tree(NB), init=rough(51 + N + Nt))
+        full = g.substitution_mask
+        if not full((2, 0, 0, 0))[z, y, x]:
+            continue
+        seen += 1
+
+        def mask(key, full=full, p=(z, y, x)):
+            m = full(key)
+            if key == (2, 0, 0, 0):
+                m[p] = False
+            return m
+        g.substitution_mask = mask
+        g.substitute()
+        tl, f = _final_field(g, N)
+        ra, rc = _residuals(tl, f, N, Nt)
+        assert max(ra, rc) > 1e-6, (pat, (x, y, z), ra, rc)
+    assert seen == (7 if Nt else (3 if N > 2 else 3))
+
+
+# ------------------------------------------------------------ detail band
+def _planted(g, key_plant, pos):
+    """Block norms with every block's detail array zero except one unit
+    detail of ``key_plant`` at local (x, y, z)."""
+    nb = g.nb
+
+    def fake(k):
+        a = np.zeros((nb, nb, nb))
+        if k == key_plant:
+            a[pos[2], pos[1], pos[0]] = 1.0
+        return a
+    g.block_details = fake
+    return g.norms()
+
+
+@pytest.mark.parametrize("N,Nt", WAVELETS)
+def test_detail_band_placement(N, Nt):
+    nb = NB
+    Ef, Eb = og.DETAIL_EXT[(N, Nt)]
+    t = TABLE3[(N, Nt)]
+    assert (Ef, Eb) == (t["ef3"], t["eb3"])
+    g = og.Grid(nb, N, Nt)
+    g.set_tree(octant_tree(nb))
+    b = (2, 0, 0, 0)
+    nxt = (2, 1, 0, 0)      # same-level neighbour behind b along x
+    mid = nb // 2 + 1
+    # behind b: the neighbour's points 0 .. Eb-1 along x are in b's band
+    if Eb:
+        assert _planted(g, nxt, (Eb - 1, mid, mid))[b] == 1.0
+    assert _planted(g, nxt, (Eb, mid, mid))[b] == 0.0
+    # in front of nxt (b is its front neighbour): b's points nb-Ef .. nb-1
+    if Ef:
+        assert _planted(g, b, (nb - Ef, mid, mid))[nxt] == 1.0
+    assert _planted(g, b, (nb - Ef - 1, mid, mid))[nxt] == 0.0
+    # the far side of a neighbour never enters
+    assert _planted(g, nxt, (nb - 1, mid, mid))[b] == 0.0
+    # coarser and finer neighbours do not enter (same-level reading)
+    coarse = (1, 1, 0, 0)   # across the -x face of b (periodic)
+    assert _planted(g, coarse, (nb - 1, 1, 1))[b] == 0.0
+    assert _planted(g, b, (0, mid, mid))[coarse] == 0.0
+
+
+@pytest.mark.parametrize("N,Nt", WAVELETS)
+def test_detail_band_covers_the_neighbour_slab(N, Nt):
+    """R-EXT covers the details that coarsening a block would discard in its
+    same-level neighbours: the band behind (in front of) a block reaches as
+    far as the front (back) substitution slab of the neighbour there."""
+    g = og.Grid(NB, N, Nt)
+    Ef, Eb = og.DETAIL_EXT[(N, Nt)]
+    lo_f, hi_f = g.substitution_slab((-1, 0, 0))[0]
+    lo_b, hi_b = g.substitution_slab((1, 0, 0))[0]
+    # unlifted slabs take even points of the facing axis only
+    front = [x for x in range(lo_f, hi_f) if Nt or x % 2 == 0]
+    back = [x for x in range(lo_b, hi_b) if Nt or x % 2 == 0]
+    assert (max(front) + 1 if front else 0) == Eb
+    assert (NB - min(back) if back else 0) == Ef
