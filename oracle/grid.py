@@ -358,22 +358,34 @@ class Grid:
             out[sel] = -acc
         return z, y, x, out
 
-    def substitute(self):
+    def substitute(self, keys=None):
         """Substitution step of sections 2.2.4 and 2.3 on every fine block
         next to a coarser leaf, in degree order: all degree-1 points of every
         block, then degree 2, then degree 3 (each degree reads the values the
         lower degrees were given, in its own block and in its same-level
         neighbours; ghost values in coarser regions come from the samples
         before the substitution, READING R-ORDER).  Returns the number of
-        points written."""
-        pre = {k: v.copy() for k, v in self.blocks.items()}
-        masks = {k: self.substitution_mask(k) for k in sorted(self.blocks)}
-        self._pre = pre
+        points written.
+
+        With ``keys``, only those blocks' substituted values are exact: the
+        degrees 1 and 2 run on them and their same-level neighbours (whose
+        values their stencils read), degree 3 on them alone (a sampled check
+        of a large grid; other blocks are left partly substituted)."""
+        if keys is None:
+            inner = ring = set(self.blocks)
+        else:
+            inner = {tuple(k) for k in keys}
+            ring = set(inner)
+            for k in inner:
+                ring |= {n for n in self.leaf_neighbors(k) if n[0] == k[0]}
+        masks = {k: self.substitution_mask(k) for k in sorted(ring)}
+        touched = {k for k, m in masks.items() if m.any()}
+        self._pre = {k: (v.copy() if k in touched else v) for k, v in self.blocks.items()}
         n = 0
         for deg in (1, 2, 3):
             writes = []
             for key, M in masks.items():
-                if M.any():
+                if key in touched and (deg < 3 or key in inner):
                     writes.append((key,) + self.substitution_values(key, deg, M))
             for key, z, y, x, v in writes:
                 self._blocks[key][z, y, x] = v

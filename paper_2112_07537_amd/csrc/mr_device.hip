@@ -421,8 +421,6 @@ __global__ __launch_bounds__(256) void k_gview(DevGrid<T> g, const GItem* __rest
     }
   }
   __syncthreads();
-  constexpr int64_t nb3 = (int64_t)NB * NB * NB;
-  const bool slab = (it.sel & 16) != 0;
   {  // z: lines (x, y) of T2, pairs along z, written out
     const int nl = fs[0] * fs[1], nseg = (np[2] + K - 1) / K;
     const int plane = fs[0] * fs[1];
@@ -434,32 +432,7 @@ __global__ __launch_bounds__(256) void k_gview(DevGrid<T> g, const GItem* __rest
       const int x = it.lo[0] + qx, y = it.lo[1] + qy;
       const T* src = T2 + l;
       const int j0 = sg * K, jn = min(K, np[2] - j0);
-      if (slab) {
-        // selector of section 2.2.4 for the two parities of z (the pair
-        // starts on an even z)
-        bool take[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int par[3] = {x & 1, y & 1, h};
-          if (it.sel & 8) {
-            take[h] = (par[0] | par[1] | par[2]) != 0;
-          } else {
-            bool t = true, tang_odd = false;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              if (it.sel & (1 << a)) t = t && (par[a] == 0);
-              else tang_odd = tang_odd || (par[a] == 1);
-            }
-            take[h] = t && tang_odd;
-          }
-        }
-        T* col = g.field + m * nb3 + y * NB + x;
-        segment(src, plane, j0, jn, [&](int j, T ev, T od) {
-          const int z0 = it.lo[2] + 2 * j - e[2];
-          if (take[0] && z0 >= it.lo[2]) col[z0 * (NB * NB)] = ev;
-          if (take[1] && z0 + 1 < it.hi[2]) col[(z0 + 1) * (NB * NB)] = od;
-        });
-      } else {
+      {
         // region of the column and its place in that region's patch box
         // (depth dw on the axes outside the block); a pair never straddles
         // a region boundary in z (both are even)
@@ -530,6 +503,189 @@ __device__ __forceinline__ void make_desc(const DevGrid<T>& g, int b, int r, Des
   d.sz = sx * sy;
   d.off = po - lx - (int64_t)ly * sx - (int64_t)lz * sx * sy;
   d.patch = 1;
+}
+
+// ------------------------------------------------------------ substitution
+// Slab membership (sections 2.2.2, 2.2.4): point (x, y, z) of a fine block
+// whose regions with a coarser owner are the set bits of cmask (bit r =
+// region rx + 3 ry + 9 rz).  Facing a coarser region in direction d, the
+// slab spans [0, FL) on axes with d = -1 and [BL, NB) on axes with d = +1;
+// lifted, it takes every point with an odd index; unlifted, the points even
+// on the facing axes and odd on a tangential one.
+template <int N, int NT, int NB>
+__device__ __forceinline__ bool in_slabs(int cmask, int x, int y, int z) {
+  constexpr int FL = NT ? N : N - 1;
+  constexpr int BL = NT ? NB - N + 1 : NB - N + 2;
+  const int px = x & 1, py = y & 1, pz = z & 1;
+  if (NT && (px | py | pz) == 0) return false;
+  const int lx = x < FL, hx = x >= BL, ly = y < FL, hy = y >= BL, lz = z < FL, hz = z >= BL;
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    if ((dz < 0 && !lz) || (dz > 0 && !hz)) continue;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      if ((dy < 0 && !ly) || (dy > 0 && !hy)) continue;
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        if ((dx < 0 && !lx) || (dx > 0 && !hx)) continue;
+        if (dx == 0 && dy == 0 && dz == 0) continue;
+        if (!((cmask >> ((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1))) & 1)) continue;
+        if (NT) return true;
+        const bool even_facing = (dx == 0 || !px) && (dy == 0 || !py) && (dz == 0 || !pz);
+        const bool odd_tang = (dx == 0 && px) || (dy == 0 && py) || (dz == 0 && pz);
+        if (even_facing && odd_tang) return true;
+      }
+    }
+  }
+  return false;
+}
+
+// New value of a point of parity (PX, PY, PZ) (section 2.3, 1D sign of
+// section 2.2.4): minus the non-central taps of the tensor product of G^a
+// over its odd axes, read from the staged region V around element i.  The
+// taps are summed in one fixed order, so every item that computes the point
+// gets the same bits.
+template <typename T, int N, int PX, int PY, int PZ>
+__device__ __forceinline__ T subst_point(const T* V, int i, int sy, int sz) {
+  constexpr int RX = PX ? N - 1 : 0, RY = PY ? N - 1 : 0, RZ = PZ ? N - 1 : 0;
+  T acc = T(0);
+#pragma unroll
+  for (int oz = -RZ; oz <= RZ; ++oz) {
+    if (oz != 0 && !(oz & 1)) continue;
+#pragma unroll
+    for (int oy = -RY; oy <= RY; ++oy) {
+      if (oy != 0 && !(oy & 1)) continue;
+#pragma unroll
+      for (int ox = -RX; ox <= RX; ++ox) {
+        if (ox != 0 && !(ox & 1)) continue;
+        if (ox == 0 && oy == 0 && oz == 0) continue;
+        constexpr double one = 1.0;
+        const double w = (PZ ? Ga<N>::c(oz) : one) * (PY ? Ga<N>::c(oy) : one) *
+                         (PX ? Ga<N>::c(ox) : one);
+        acc += T(w) * V[i + ox + oy * sy + oz * sz];
+      }
+    }
+  }
+  return -acc;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ T subst_any(const T* V, int i, int par, int sy, int sz) {
+  switch (par) {
+    case 1: return subst_point<T, N, 1, 0, 0>(V, i, sy, sz);
+    case 2: return subst_point<T, N, 0, 1, 0>(V, i, sy, sz);
+    case 4: return subst_point<T, N, 0, 0, 1>(V, i, sy, sz);
+    case 3: return subst_point<T, N, 1, 1, 0>(V, i, sy, sz);
+    case 5: return subst_point<T, N, 1, 0, 1>(V, i, sy, sz);
+    case 6: return subst_point<T, N, 0, 1, 1>(V, i, sy, sz);
+    default: return subst_point<T, N, 1, 1, 1>(V, i, sy, sz);
+  }
+}
+
+// One workgroup per substitution item: a box of fine block F's slab points.
+// F's ghost-filled values over the box widened by N-1 points on every axis
+// (the reach of G^a) are staged in LDS: F's own points, same-level
+// neighbours' points and, in coarser regions, F's c->f patches, which hold
+// the refinement of the samples from before the substitution (the patch
+// launch runs first).  A box point's chain of stencils (degree 3 -> 2 -> 1
+// -> 0, one axis per step) only reads points whose coordinate on every axis
+// lies in the box or is even, so only those are staged.  Then, degree 1 and
+// then degree 2, every slab point of F in the staged region whose stencil
+// lies inside it is replaced in LDS; finally the box's slab points (degree 3
+// computed last) are written to the field.  With 26-neighbour 2:1 balance no
+// finer region lies within the widened box of a slab.
+//
+// Items run in any order and each writes only its own box (the host cuts a
+// block's slabs into disjoint boxes), but reads points of other boxes, its
+// own block's and its same-level neighbours'.  Every slab point that a box
+// point depends on, in F or in a same-level neighbour (with that
+// neighbour's own coarser regions), is recomputed here from all-even points
+// and points outside every slab, which no item writes; so whether a staged
+// slab value was read before or after its own item wrote it never matters,
+// and the result does not depend on the order of the items.
+template <typename T, int N, int NT, int NB>
+__global__ __launch_bounds__(256) void k_subst(DevGrid<T> g, const GItem* __restrict__ items) {
+  extern __shared__ unsigned char lds_raw[];
+  T* V = reinterpret_cast<T*>(lds_raw);
+  __shared__ Desc desc[27];
+  __shared__ int32_t cd[27];   // coarser-region mask of the block owning each
+                               // region at F's level, -1 for other levels
+  constexpr int R = N - 1;
+  const GItem it = items[xcd_item(blockIdx.x, gridDim.x)];
+  const int F = it.blk;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid < 27) {
+    make_desc(g, F, tid, desc[tid]);
+    const int rx = tid % 3, ry = (tid / 3) % 3, rz = tid / 9;
+    const int cx = rx == 0 ? 0 : (rx == 1 ? 1 : 3);
+    const int cy = ry == 0 ? 0 : (ry == 1 ? 1 : 3);
+    const int cz = rz == 0 ? 0 : (rz == 1 ? 1 : 3);
+    const int o = g.cmap[F * 64 + (cz * 4 + cy) * 4 + cx];
+    cd[tid] = (tid == 13) ? g.cdir[F] : (g.poff[(int64_t)F * 27 + tid] < 0 ? g.cdir[o] : -1);
+  }
+  // slab membership of a staged point, in the frame of the block owning it
+  auto in_s = [&](int x, int y, int z) -> bool {
+    const int rx = x < 0 ? 0 : (x < NB ? 1 : 2);
+    const int ry = y < 0 ? 0 : (y < NB ? 1 : 2);
+    const int rz = z < 0 ? 0 : (z < NB ? 1 : 2);
+    const int m = cd[rx + 3 * ry + 9 * rz];
+    return m > 0 && in_slabs<N, NT, NB>(m, x - (rx - 1) * NB, y - (ry - 1) * NB, z - (rz - 1) * NB);
+  };
+  int r0[3], rs[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r0[a] = it.lo[a] - R;
+    rs[a] = it.hi[a] - it.lo[a] + 2 * R;
+  }
+  const int sy = rs[0], sz = rs[0] * rs[1];
+  const int n = sz * rs[2];
+  __syncthreads();
+  {
+    Iter3 q(tid, nt, rs[0], rs[1]);
+    for (int i = tid; i < n; i += nt, q.advance()) {
+      const int x = r0[0] + q.x, y = r0[1] + q.y, z = r0[2] + q.z;
+      const bool lat = (!(x & 1) || (x >= it.lo[0] && x < it.hi[0])) &&
+                       (!(y & 1) || (y >= it.lo[1] && y < it.hi[1])) &&
+                       (!(z & 1) || (z >= it.lo[2] && z < it.hi[2]));
+      if (!lat) continue;
+      const int rx = x < 0 ? 0 : (x < NB ? 1 : 2);
+      const int ry = y < 0 ? 0 : (y < NB ? 1 : 2);
+      const int rz = z < 0 ? 0 : (z < NB ? 1 : 2);
+      const Desc d = desc[rx + 3 * ry + 9 * rz];
+      V[i] = (d.patch ? g.patch : g.field)[d.off + x + (int64_t)y * d.sy + (int64_t)z * d.sz];
+    }
+  }
+  __syncthreads();
+  // degrees 1 and 2 over the staged region, in place: degree k reads only
+  // points of lower degree
+#pragma unroll 1
+  for (int deg = 1; deg <= 2; ++deg) {
+    Iter3 q(tid, nt, rs[0], rs[1]);
+    for (int i = tid; i < n; i += nt, q.advance()) {
+      const int x = r0[0] + q.x, y = r0[1] + q.y, z = r0[2] + q.z;
+      const int px = x & 1, py = y & 1, pz = z & 1;
+      if (px + py + pz != deg) continue;
+      if ((px && (q.x < R || q.x >= rs[0] - R)) || (py && (q.y < R || q.y >= rs[1] - R)) ||
+          (pz && (q.z < R || q.z >= rs[2] - R)))
+        continue;
+      if (!in_s(x, y, z)) continue;
+      V[i] = subst_any<T, N>(V, i, px | (py << 1) | (pz << 2), sy, sz);
+    }
+    __syncthreads();
+  }
+  {
+    const int b0 = it.hi[0] - it.lo[0], b1 = it.hi[1] - it.lo[1];
+    const int bn = b0 * b1 * (it.hi[2] - it.lo[2]);
+    T* fb = g.field + (int64_t)F * (NB * NB * NB);
+    Iter3 q(tid, nt, b0, b1);
+    for (int i = tid; i < bn; i += nt, q.advance()) {
+      const int x = it.lo[0] + q.x, y = it.lo[1] + q.y, z = it.lo[2] + q.z;
+      const int par = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
+      if (!par || !in_slabs<N, NT, NB>(cd[13], x, y, z)) continue;
+      const int li = ((q.z + R) * rs[1] + (q.y + R)) * rs[0] + (q.x + R);
+      fb[(z * NB + y) * NB + x] = par == 7 ? subst_point<T, N, 1, 1, 1>(V, li, sy, sz) : V[li];
+    }
+  }
 }
 
 // ------------------------------------------------------ restriction (f->c)
@@ -1371,6 +1527,24 @@ void launch_gview(bool f32, const void* dg, Wavelet w, const GItem* items, int n
   if (n <= 0) return;
   if (f32) gview_t<float>(dg, w, items, n, lds, s);
   else gview_t<double>(dg, w, items, n, lds, s);
+}
+
+template <typename T, int NB>
+static void subst_nb(const DevGrid<T>& g, Wavelet w, const GItem* items, int n, int lds, hipStream_t s) {
+  MR_WAVELET_SWITCH(w, MR_LAUNCH((k_subst<T, N_, NT_, NB>), dim3(n), dim3(256), lds, s, g, items));
+}
+template <typename T>
+static void subst_t(const void* dg, Wavelet w, const GItem* items, int n, int lds, hipStream_t s) {
+  const DevGrid<T>& g = *static_cast<const DevGrid<T>*>(dg);
+  if (g.nb == 8) subst_nb<T, 8>(g, w, items, n, lds, s);
+  else if (g.nb == 16) subst_nb<T, 16>(g, w, items, n, lds, s);
+  else subst_nb<T, 24>(g, w, items, n, lds, s);
+}
+void launch_subst(bool f32, const void* dg, Wavelet w, const GItem* items, int n, int lds,
+                  hipStream_t s) {
+  if (n <= 0) return;
+  if (f32) subst_t<float>(dg, w, items, n, lds, s);
+  else subst_t<double>(dg, w, items, n, lds, s);
 }
 
 template <typename T, int NB>

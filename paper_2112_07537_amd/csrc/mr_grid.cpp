@@ -118,18 +118,16 @@ struct DevBuf {
 };
 
 struct Lists {
-  std::vector<GItem> g;
+  std::vector<GItem> g;   // c->f patch items (one launch)
+  std::vector<GItem> s;   // substitution items (one launch, after the patches)
   std::vector<RItem> r;
-  int lds_g = 0;
-  // c->f launch groups [gb[i], gb[i+1]): substitution items one level at a
-  // time, finest first, then every patch item (READING R-ORDER)
-  std::vector<int> gb;
+  int lds_g = 0, lds_s = 0;
   // f->c items grouped by pass-1 column length (extent along y or z):
   // classes <= 3, <= 6, <= 12 at [rcls[c], rcls[c+1]) with their LDS sizes
   int rcls[4] = {0, 0, 0, 0};
   int lds_rc[3] = {0, 0, 0};
   int64_t out_points = 0;
-  DevBuf dg, dr;
+  DevBuf dg, ds, dr;
 };
 
 struct Prof {
@@ -139,10 +137,12 @@ struct Prof {
     int fam;
   };
   std::vector<Rec> recs;
-  int64_t points[4] = {0, 0, 0, 0};
+  int64_t points[5] = {0, 0, 0, 0, 0};
 };
 
-static const char* kFam[4] = {"rhs", "details", "ghost_refine", "ghost_restrict"};
+static const int kNumFam = 5;
+static const char* kFam[kNumFam] = {"rhs", "details", "ghost_refine", "ghost_restrict",
+                                    "ghost_subst"};
 
 // Host-side phases of an adaptation (wall clock, stream work included where
 // the phase waits for it): criterion (ghosts + transform + norms to host),
@@ -184,7 +184,7 @@ struct mr_grid {
   // device
   std::vector<DevBuf> fields, alts;
   DevBuf tmpA, tmpB;
-  DevBuf d_lev, d_ijk, d_cmap, d_poff, d_patch, d_err, d_cbase, d_cstep;
+  DevBuf d_lev, d_ijk, d_cmap, d_poff, d_patch, d_err, d_cbase, d_cstep, d_cdir;
   // second patch buffer of the same layout, for the later stages of a fused
   // step while the detail pass still reads the first (allocated on demand)
   DevBuf d_patch2;
@@ -407,6 +407,14 @@ static int rview_lds(const RItem& it, int H, size_t esz) {
 // values do not depend on the tiling, and the f->c tiling is fixed.
 static const int kLdsBudgetRefine = 20 * 1024;
 static const int kLdsBudgetRestrict = 24 * 1024;
+static const int kLdsBudgetSubst = 32 * 1024;
+
+// LDS of a substitution item: its box widened by N-1 points on every axis.
+static int subst_lds(const GItem& it, int N, size_t esz) {
+  size_t v = esz;
+  for (int a = 0; a < 3; ++a) v *= size_t(it.hi[a] - it.lo[a] + 2 * (N - 1));
+  return int(v);
+}
 
 // Split a box along its longest axis until the LDS estimate fits the budget.
 template <typename Item, typename F>
@@ -462,34 +470,39 @@ static void box_subtract(const GItem& a, const GItem& b, std::vector<GItem>& out
   // what is left of a lies inside b
 }
 
-// Work lists of one ghost reconstruction at depth D: substitution slabs and
-// c->f patches (one launch), then f->c restrictions by the fine blocks (a
-// second launch, which reads the fine blocks' substituted values and their
-// c->f patches).  c->f patches are filled to max(D, reach of H^a) so that a
-// fine block's restriction window is covered by its own ghost layer.
+// Work lists of one ghost reconstruction at depth D, in launch order
+// (READING R-ORDER, the ghosting algorithms' Part 1 before Part 2): c->f
+// patches (refined from the samples as they stand), then the substitution of
+// every fine block's slabs (reading those patches), then f->c restrictions by
+// the fine blocks (reading their substituted values and their c->f
+// patches).  c->f patches are filled to max(D, reach of H^a, N-1): a fine
+// block's restriction window and its substitution stencils are covered by
+// its own ghost layer.
 static mr_status build_lists(mr_grid* g, int D, Lists& L) {
   L.g.clear();
+  L.s.clear();
   L.r.clear();
   L.out_points = 0;
   const int nb = g->nb, N = g->N, Nt = g->Nt, Dw = g->Dw;
   const int H = Hreach(N, Nt);
-  const int Dc = std::min(Dw, std::max(D, H));
+  const int Dc = std::min(Dw, std::max(std::max(D, H), N - 1));
   const size_t esz = g->esz;
   auto glds = [&](const GItem& it) { return gview_lds(it, N, esz); };
+  auto slds = [&](const GItem& it) { return subst_lds(it, N, esz); };
   auto rlds = [&](const RItem& it) { return rview_lds(it, H, esz); };
   const int n = int(g->leaves.size());
   const int hb = nb / 2;
   // blocks are split into contiguous chunks built on host threads; the
   // chunks' items are concatenated in block order
   struct Part {
-    std::vector<GItem> g;
+    std::vector<GItem> g, s;
     std::vector<RItem> r;
     int64_t pts = 0;
     bool ok = true;
   };
   auto one_block = [&](int b, Part& P) -> bool {
     const int Lb = g->leaves[b].L;
-    std::vector<GItem> slabs;   // lifted wavelets: made disjoint below
+    std::vector<GItem> slabs;   // made disjoint below
     for (int r = 0; r < 27; ++r) {
       if (r == 13) continue;
       const int lr = region_level(g, b, r);
@@ -501,13 +514,13 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
         // c->f patches are merged per side below
         // substitution slab of this interface (READING R-SUB), unless a
         // coarser region facing a proper subset of the same axes exists: its
-        // slab contains this one (and the substituted values do not depend
-        // on which item computes them)
+        // slab contains this one
         GItem sb{};
         sb.blk = b;
         sb.sel = (Nt ? 8 : 0) | 16;
+        int facing = 0;
         for (int a = 0; a < 3; ++a)
-          if (rr[a] != 1) sb.sel |= (1 << a);
+          if (rr[a] != 1) facing |= (1 << a);
         bool sempty = false;
         for (int a = 0; a < 3; ++a) {
           const int d = rr[a] - 1;
@@ -521,8 +534,7 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
           }
           if (sb.hi[a] <= sb.lo[a]) sempty = true;
         }
-        if (!Nt && (sb.sel & 7) == 7) sempty = true;  // corner: no tangential axis
-        const int facing = sb.sel & 7;
+        if (!Nt && facing == 7) sempty = true;  // corner: no tangential axis
         bool covered = false;
         for (int sub = 1; sub < 8 && !covered; ++sub) {
           if ((sub & facing) != sub || sub == facing) continue;
@@ -530,10 +542,7 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
           for (int a = 0; a < 3; ++a, mul *= 3) r2 += mul * ((sub >> a) & 1 ? rr[a] : 1);
           if (region_level(g, b, r2) < Lb) covered = true;
         }
-        if (!sempty && !covered) {
-          if (Nt) slabs.push_back(sb);
-          else push_tiled(P.g, sb, glds, kLdsBudgetRefine);
-        }
+        if (!sempty && !covered) slabs.push_back(sb);
       } else {
         // f->c: each finer leaf covering this region restricts its part
         region_box(nb, D, r, blo, bhi);
@@ -601,10 +610,9 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
         }
         push_tiled(P.g, pt, glds, kLdsBudgetRefine);
       }
-    // With lifting every slab takes the same points (at least one odd index),
-    // so overlapping slabs (two faces meet along an edge) can be cut into
-    // disjoint boxes: each point is then written by exactly one item, and
-    // the result does not depend on which of two items writes last.
+    // Overlapping slabs (two faces meet along an edge) are cut into disjoint
+    // boxes, so each point is written by exactly one item; the kernel decides
+    // per point from all of the block's coarser regions whether it is taken.
     if (!slabs.empty()) {
       std::vector<GItem> acc, pieces, next;
       for (const GItem& sl : slabs) {
@@ -616,7 +624,7 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
         }
         acc.insert(acc.end(), pieces.begin(), pieces.end());
       }
-      for (const GItem& pc : acc) push_tiled(P.g, pc, glds, kLdsBudgetRefine);
+      for (const GItem& pc : acc) push_tiled(P.s, pc, slds, kLdsBudgetSubst);
     }
     return true;
   };
@@ -631,6 +639,7 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
   for (Part& P : parts) {
     if (!P.ok) return fail(MR_EINVAL, "finer region not covered by level+1 leaves");
     L.g.insert(L.g.end(), P.g.begin(), P.g.end());
+    L.s.insert(L.s.end(), P.s.begin(), P.s.end());
     L.r.insert(L.r.end(), P.r.begin(), P.r.end());
     L.out_points += P.pts;
   }
@@ -647,24 +656,8 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
   }
   L.lds_g = 0;
   for (const GItem& it : L.g) L.lds_g = std::max(L.lds_g, gview_lds(it, N, esz));
-  {
-    // Launch order (READING R-ORDER).  A substitution reads the level-(L-1)
-    // points around its slab, which in a coarser neighbour are all of that
-    // neighbour's points; the neighbour's own substitution may rewrite some
-    // of them.  Substitutions therefore run one level at a time, finest
-    // first, so each reads the values from before any substitution.  c->f
-    // patches read substituted values, so they run after all of them.  Block
-    // order is kept inside each group.
-    auto key = [&](const GItem& it) {
-      return (it.sel & 16) ? 64 - g->leaves[it.blk].L : 128;
-    };
-    std::stable_sort(L.g.begin(), L.g.end(),
-                     [&](const GItem& a, const GItem& b) { return key(a) < key(b); });
-    L.gb.assign(1, 0);
-    for (size_t i = 1; i < L.g.size(); ++i)
-      if (key(L.g[i]) != key(L.g[i - 1])) L.gb.push_back(int(i));
-    if (!L.g.empty()) L.gb.push_back(int(L.g.size()));
-  }
+  L.lds_s = 0;
+  for (const GItem& it : L.s) L.lds_s = std::max(L.lds_s, subst_lds(it, N, esz));
   {
     auto cls = [](const RItem& it) {
       const int q = std::min(it.hi[1] - it.lo[1], it.hi[2] - it.lo[2]);
@@ -686,11 +679,15 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
     L.r.swap(sorted);
   }
   const int lds_r = std::max(L.lds_rc[0], std::max(L.lds_rc[1], L.lds_rc[2]));
-  if (L.lds_g > 64 * 1024 || lds_r > 64 * 1024) return fail(MR_EINVAL, "ghost work item exceeds LDS");
+  if (L.lds_g > 64 * 1024 || lds_r > 64 * 1024 || L.lds_s > 64 * 1024)
+    return fail(MR_EINVAL, "ghost work item exceeds LDS");
   HIPCHK(L.dg.ensure(std::max<size_t>(1, L.g.size()) * sizeof(GItem)));
+  HIPCHK(L.ds.ensure(std::max<size_t>(1, L.s.size()) * sizeof(GItem)));
   HIPCHK(L.dr.ensure(std::max<size_t>(1, L.r.size()) * sizeof(RItem)));
   if (!L.g.empty())
     HIPCHK(hipMemcpyAsync(L.dg.p, L.g.data(), L.g.size() * sizeof(GItem), hipMemcpyHostToDevice, g->stream));
+  if (!L.s.empty())
+    HIPCHK(hipMemcpyAsync(L.ds.p, L.s.data(), L.s.size() * sizeof(GItem), hipMemcpyHostToDevice, g->stream));
   if (!L.r.empty())
     HIPCHK(hipMemcpyAsync(L.dr.p, L.r.data(), L.r.size() * sizeof(RItem), hipMemcpyHostToDevice, g->stream));
   return MR_OK;
@@ -738,7 +735,15 @@ static mr_status commit_tree_impl(mr_grid* g) {
       if (g->poff[size_t(b) * 27 + r] >= 0) g->poff[size_t(b) * 27 + r] += base;
   }
   g->patch_elems = cur;
-  std::vector<int32_t> lev(n), ijk(3 * size_t(n));
+  std::vector<int32_t> lev(n), ijk(3 * size_t(n)), cdir(n);
+  parallel_for(size_t(n), [&](size_t lo_b, size_t hi_b) {
+    for (size_t b = lo_b; b < hi_b; ++b) {
+      int32_t m = 0;
+      for (int r = 0; r < 27; ++r)
+        if (r != 13 && region_level(g, int(b), r) < g->leaves[b].L) m |= 1 << r;
+      cdir[b] = m;
+    }
+  });
   for (int b = 0; b < n; ++b) {
     lev[b] = g->leaves[b].L;
     ijk[3 * b] = g->leaves[b].i;
@@ -749,6 +754,7 @@ static mr_status commit_tree_impl(mr_grid* g) {
   HIPCHK(g->d_ijk.ensure(std::max(1, 3 * n) * sizeof(int32_t)));
   HIPCHK(g->d_cmap.ensure(std::max(1, 64 * n) * sizeof(int32_t)));
   HIPCHK(g->d_poff.ensure(std::max(1, 27 * n) * sizeof(int64_t)));
+  HIPCHK(g->d_cdir.ensure(std::max(1, n) * sizeof(int32_t)));
   HIPCHK(g->d_patch.ensure(std::max<int64_t>(1, cur) * g->esz));
   HIPCHK(g->d_bands.ensure(std::max(1, 27 * n) * sizeof(double)));
   HIPCHK(g->d_norms.ensure(std::max(1, n) * sizeof(double)));
@@ -757,6 +763,7 @@ static mr_status commit_tree_impl(mr_grid* g) {
     HIPCHK(hipMemcpyAsync(g->d_ijk.p, ijk.data(), 3 * n * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
     HIPCHK(hipMemcpyAsync(g->d_cmap.p, g->cmap.data(), 64 * size_t(n) * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
     HIPCHK(hipMemcpyAsync(g->d_poff.p, g->poff.data(), 27 * size_t(n) * sizeof(int64_t), hipMemcpyHostToDevice, g->stream));
+    HIPCHK(hipMemcpyAsync(g->d_cdir.p, cdir.data(), size_t(n) * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
     HIPCHK(g->d_cbase.ensure(64 * size_t(n) * sizeof(int64_t)));
     HIPCHK(g->d_cstep.ensure(64 * size_t(n) * sizeof(int32_t)));
     build_cell_tables(g);
@@ -779,6 +786,7 @@ static DevGrid<T> view(mr_grid* g, void* field, void* patch = nullptr) {
   d.ijk = static_cast<const int32_t*>(g->d_ijk.p);
   d.cmap = static_cast<const int32_t*>(g->d_cmap.p);
   d.poff = static_cast<const int64_t*>(g->d_poff.p);
+  d.cdir = static_cast<const int32_t*>(g->d_cdir.p);
   d.cbase = static_cast<const int64_t*>(g->d_cbase.p);
   d.cstep = static_cast<const int32_t*>(g->d_cstep.p);
   d.field = static_cast<T*>(field);
@@ -835,18 +843,27 @@ static void ghost_fill(mr_grid* g, void* field, Lists& L, void* patch = nullptr)
   const Wavelet w{g->N, g->Nt};
   const bool plain = g->cfg.exec_mode == 1;
   hipEvent_t a = nullptr, b = nullptr;
-  // substitution one level at a time (finest first), then the c->f patches;
-  // each group is one launch, timed on its own
+  // c->f patches, then the substitution (which reads them), each one launch
   const GItem* gi = static_cast<const GItem*>(L.dg.p);
-  for (size_t k = 0; k + 1 < L.gb.size(); ++k) {
-    const int i0 = L.gb[k], i1 = L.gb[k + 1];
+  const GItem* si = static_cast<const GItem*>(L.ds.p);
+  const int ng = int(L.g.size()), ns = int(L.s.size());
+  if (ng) {
     prof_begin(g, 2, &a, &b, !plain);
     if (plain) {
-      for (int i = i0; i < i1; ++i) launch_gview(g->f32, v.raw, w, gi + i, 1, L.lds_g, g->stream);
+      for (int i = 0; i < ng; ++i) launch_gview(g->f32, v.raw, w, gi + i, 1, L.lds_g, g->stream);
     } else {
-      launch_gview(g->f32, v.raw, w, gi + i0, i1 - i0, L.lds_g, g->stream);
+      launch_gview(g->f32, v.raw, w, gi, ng, L.lds_g, g->stream);
     }
     prof_end(g, 2, a, b, !plain, L.out_points);
+  }
+  if (ns) {
+    prof_begin(g, 4, &a, &b, !plain);
+    if (plain) {
+      for (int i = 0; i < ns; ++i) launch_subst(g->f32, v.raw, w, si + i, 1, L.lds_s, g->stream);
+    } else {
+      launch_subst(g->f32, v.raw, w, si, ns, L.lds_s, g->stream);
+    }
+    prof_end(g, 4, a, b, !plain, L.out_points);
   }
   // one launch per column-length class (the classes are independent)
   static const int kMaxq[3] = {3, 6, 12};
@@ -1398,8 +1415,8 @@ static void free_grid(mr_grid* g) {
   for (auto& b : g->alts) b.release();
   DevBuf* bufs[] = {&g->tmpA, &g->tmpB, &g->d_lev, &g->d_ijk, &g->d_cmap, &g->d_poff, &g->d_patch,
                     &g->d_err, &g->d_bands, &g->d_norms, &g->d_icpar, &g->d_mom,
-                    &g->stage.dg, &g->stage.dr, &g->wide.dg, &g->wide.dr, &g->ad_pairs,
-                    &g->d_cbase, &g->d_cstep, &g->d_patch2,
+                    &g->stage.dg, &g->stage.ds, &g->stage.dr, &g->wide.dg, &g->wide.ds,
+                    &g->wide.dr, &g->ad_pairs, &g->d_cbase, &g->d_cstep, &g->d_cdir, &g->d_patch2,
                     &g->ad_items, &g->ad_scr, &g->ad_det, &g->ad_slot};
   for (DevBuf* b : bufs) b->release();
   if (g->aux) {
@@ -1764,7 +1781,7 @@ mr_status mr_prof_read(mr_grid* g, const char* kernel, double* total_ms, int64_t
                        int64_t* points_per_launch) {
   if (!g || !kernel || !total_ms || !launches) return fail(MR_EINVAL, "null argument");
   int fam = -1;
-  for (int f = 0; f < 4; ++f)
+  for (int f = 0; f < kNumFam; ++f)
     if (std::strcmp(kernel, kFam[f]) == 0) fam = f;
   for (int f = 0; f < 4; ++f)
     if (std::strcmp(kernel, kHostPhase[f]) == 0) {
@@ -1805,9 +1822,7 @@ mr_status mr_tree_stats(const mr_grid* g, int64_t out[10]) {
   }
   out[0] = int64_t(g->leaves.size());
   out[1] = g->stage.out_points;
-  int64_t subs = 0;
-  for (const GItem& it : g->stage.g) subs += (it.sel & 16) != 0;
-  out[2] = subs;
+  out[2] = int64_t(g->stage.s.size());
   out[3] = hi;
   out[4] = lo;
   out[5] = int64_t(g->stage.g.size());

@@ -14,13 +14,11 @@ namespace mr {
 // around a box of level-L points of block blk.  A patch item covers the
 // coarser regions of blk on one side (bit r of rmask set for region r);
 // each point is written into the patch of its region.  A substitution item
-// overwrites the points of blk's slab next to a coarser leaf that pass the
-// selector (section 2.2.4).
+// (sections 2.2.4, 2.3) is a box of blk's slabs next to coarser leaves; the
+// kernel replaces the box's slab points degree by degree.
 struct GItem {
   int32_t blk;      // fine block whose owner map resolves the samples
-  int32_t sel;      // bits 0..2 = axes facing the coarser leaf (substitution),
-                    // bit 3 = lifted wavelet (every non-all-even point),
-                    // bit 4 = substitution item (else patch item)
+  int32_t sel;      // bit 3 = lifted wavelet, bit 4 = substitution item
   int32_t lo[3];    // box [lo, hi) of level-L points, relative to blk's
   int32_t hi[3];    //   origin at blk's level
   int32_t rmask;    // patch item: regions (rx + 3 ry + 9 rz) written
@@ -77,6 +75,7 @@ struct DevGrid {
   const int32_t* cmap;   // [64*nblk] leaf id per half-block cell of the
                          //   4x4x4 cells covering [-nb/2, 3nb/2)^3
   const int64_t* poff;   // [27*nblk] patch offset per region, -1 if none
+  const int32_t* cdir;   // [nblk] bit r set: region r has a coarser owner
   const int64_t* cbase;  // [64*nblk] coarse-sample address table per cell
   const int32_t* cstep;  //   (see k_cell_tables)
   T* field;              // [nblk * nb^3]
@@ -103,6 +102,8 @@ struct Wavelet {
 };
 
 void launch_gview(bool f32, const void* dg, Wavelet w, const GItem* items, int n_items,
+                  int lds_bytes, hipStream_t s);
+void launch_subst(bool f32, const void* dg, Wavelet w, const GItem* items, int n_items,
                   int lds_bytes, hipStream_t s);
 void launch_cell_tables(bool f32, const void* dg, int n_blocks, hipStream_t s);
 void launch_rview(bool f32, const void* dg, Wavelet w, const RItem* items, int n_items,

@@ -142,9 +142,7 @@ def test_fused_rejects_bad_arguments():
 
 def test_fused_async_matches_sync():
     """The asynchronous form (norms left on the device, no synchronisation)
-    does the same work as the synchronous one.  Batched ghost launches are
-    reproducible to about 1e-15 of max|phi| run to run, not bit for bit, so
-    the comparison takes the parity tolerance."""
+    does the same work as the synchronous one."""
     vel = mr.velocity("shear")
     a = grid(24, 6, 2, 6, "f32")
     b = grid(24, 6, 2, 6, "f32")
@@ -161,11 +159,13 @@ def test_fused_async_matches_sync():
     b.close()
 
 
-@pytest.mark.parametrize("nb,N,Nt,fd,prec", [(24, 6, 2, 6, "f32"), (16, 4, 2, 4, "f64")])
+@pytest.mark.parametrize("nb,N,Nt,fd,prec", [(24, 6, 2, 6, "f32"), (16, 4, 2, 4, "f64"),
+                                             (16, 4, 0, 4, "f32"), (24, 6, 0, 6, "f64")])
 def test_batched_fills_repeat_bit_for_bit(nb, N, Nt, fd, prec):
-    """Lifted wavelets: every field point a ghost reconstruction writes is
-    written by one work item (disjoint substitution slabs) and the launches
-    are ordered (substitution one level at a time, then c->f), so batched
+    """Every field point a ghost reconstruction writes is written by one work
+    item (disjoint substitution boxes, lifted or not), every substituted
+    value is computed from values no item of the launch writes, and the
+    launches are ordered (c->f, substitution, f->c), so batched
     reconstructions and steps repeat bit for bit from the same state."""
     vel = mr.velocity("shear")
     out = []

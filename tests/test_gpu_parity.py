@@ -95,11 +95,11 @@ def test_ghost_parity(nb, N, Nt, fd, prec):
         for b, k in enumerate(keys):
             ref = o.ghost_block(k, d)
             err = np.abs(ext[b].astype(np.float64) - ref).max()
-            assert err <= TOL[prec] * scale * 4, (k, d, err)
+            assert err <= TOL[prec] * scale, (k, d, err)
     # substituted field itself
     got = g.field_get().astype(np.float64)
     for b, k in enumerate(keys):
-        assert np.abs(got[b] - o.blocks[k]).max() <= TOL[prec] * scale * 4
+        assert np.abs(got[b] - o.blocks[k]).max() <= TOL[prec] * scale
 
 
 @pytest.mark.parametrize("nb,N,Nt,fd", [(16, 4, 2, 4), (24, 6, 2, 6), (16, 4, 0, 4)])
@@ -117,7 +117,7 @@ def test_wide_ghost_parity(nb, N, Nt, fd):
     scale = np.abs(f).max()
     for b, k in enumerate(keys):
         ref = o.ghost_block(k, Dw)
-        assert np.abs(ext[b] - ref).max() <= 1e-12 * scale * 4, k
+        assert np.abs(ext[b] - ref).max() <= 1e-12 * scale, k
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -222,7 +222,7 @@ def test_adapt_apply_parity(nb, N, Nt, fd):
     got = g.field_get()
     scale = max(np.abs(b).max() for b in o.blocks.values())
     for b, k in enumerate(meta2):
-        assert np.abs(got[b] - o.blocks[k]).max() <= 1e-12 * scale * 4, k
+        assert np.abs(got[b] - o.blocks[k]).max() <= 1e-12 * scale, k
 
 
 def test_abi_errors_on_gpu():
