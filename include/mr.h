@@ -24,7 +24,9 @@
  *    transform, its norms, threshold comparisons and moment sums are FP64.
  *  - Host pointers passed in are caller-owned and only read/written during
  *    the call.  Device memory is owned by the library (hipMalloc) and freed
- *    by mr_grid_destroy.
+ *    by mr_grid_destroy, except the field buffers when the caller passes a
+ *    pool to mr_grid_create (they are then slices of that caller-owned
+ *    pool, never freed or grown by the library).
  *  - Streams: device work is issued on the hipStream_t given at creation;
  *    with NULL the library creates a private non-blocking stream.  mr_ghost,
  *    mr_rk3_step and mr_details with on_device = 1 are asynchronous; every
@@ -113,11 +115,26 @@ typedef struct {
   int64_t n_blocks;   /* leaves after adaptation                          */
 } mr_adapt_stats;
 
-/* Create a grid.  hip_stream: a hipStream_t, or NULL for a private stream
- * owned by the grid.  The tree starts as the
+/* Create a grid (the block-structured grid of section 2.2 with the
+ * adaptation parameters of section 2.2.5).  hip_stream: a hipStream_t, or
+ * NULL for a private stream owned by the grid.  dev_pool: NULL (the library
+ * allocates the field buffers with hipMalloc), or device memory owned by the
+ * caller, 256-byte aligned, of pool_bytes >= mr_pool_bytes(cfg) bytes, e.g.
+ * a torch uint8 tensor that the caller keeps alive until mr_grid_destroy;
+ * the library then takes the fixed-capacity buffers (fields, their
+ * adaptation alternates, two work buffers: max_blocks blocks each) from it
+ * and never frees it.  Buffers that follow the tree (ghost patches, work
+ * lists, metadata, adaptation scratch) are always the library's.  A pool
+ * that is misaligned or too small gives MR_EINVAL.  The tree starts as the
  * uniform tree at level_min with zero fields.  Warns (mr_last_error) but
  * succeeds when eps_refine/eps_coarsen <= 2^N (section 2.2.5: flip-flops). */
-mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, mr_grid** out);
+mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, void* dev_pool,
+                         size_t pool_bytes, mr_grid** out);
+
+/* Bytes a caller pool must hold for cfg: (2 n_fields + 2) buffers of
+ * max_blocks * nb^3 values of the field precision, each rounded up to a
+ * multiple of 256.  No device call. */
+mr_status mr_pool_bytes(const mr_config* cfg, size_t* bytes);
 mr_status mr_grid_destroy(mr_grid* g);
 
 /* Replace the tree by the n leaves (level[i], ijk[3*i..3*i+2]); the set must
@@ -133,10 +150,15 @@ mr_status mr_sample_ic(mr_grid* g, int32_t field, const mr_ic* ic);
 mr_status mr_init_ic(mr_grid* g, int32_t field, const mr_ic* ic, int32_t max_iter,
                      mr_adapt_stats* stats);
 
-/* Ghost reconstruction of `field` (sections 2.2.2, 2.2.4 and the ghosting
- * algorithms Part 1 / Part 2): substitution on fine blocks next to coarser
- * leaves, then ghost patches of `depth` points (0 = stencil depth
- * fd_order/2) across every resolution jump.  Asynchronous. */
+/* Ghost reconstruction of `field` (sections 2.2.2, 2.2.4, 2.3 and the
+ * ghosting algorithms Part 1 / Part 2), in this order: ghost patches of
+ * every fine block in its coarser regions (zero-detail refinement of the
+ * samples as they stand); the substitution of the slab points of every fine
+ * block next to a coarser leaf, degree 1, 2 then 3 over the whole level
+ * (section 2.3), written into the field; the patches of every coarse block
+ * inside its finer regions (restriction of the substituted finer data).
+ * Patches are `depth` points deep (0 = stencil depth fd_order/2).
+ * Asynchronous. */
 mr_status mr_ghost(mr_grid* g, int32_t field, int32_t depth);
 
 /* Copy blocks [b0, b0+nblk) of `field` with their ghost layer of `depth`
@@ -157,9 +179,12 @@ mr_status mr_details(mr_grid* g, int32_t field, double* norms, int32_t on_device
 /* Iterative adaptation (adaptation supplement): criterion, flags, policy
  * (refinement priority and propagation, 2:1, no coarsening of blocks refined
  * in this call, level bounds), refine / coarsen all fields, update step, until
- * no block changes or max_iter iterations.  An iteration whose new tree would
- * exceed max_blocks is not applied (MR_ECAPACITY); iterations already applied
- * in the same call remain.  Synchronises. */
+ * no block changes or max_iter iterations.  Transactional over the call:
+ * when an iteration's new tree would exceed max_blocks (MR_ECAPACITY) or a
+ * norm is not finite (MR_ENONFINITE), the tree and every field come back
+ * exactly as they were before the call (the substitution of the criterion's
+ * ghost reconstructions included).  The call copies every field once into a
+ * library-owned buffer of the current tree's size for this.  Synchronises. */
 mr_status mr_adapt(mr_grid* g, int32_t field, int32_t max_iter, mr_adapt_stats* stats);
 
 /* One SSP-RK3 step of `field` (time-integration supplement) with central FD
@@ -207,7 +232,7 @@ mr_status mr_moments(mr_grid* g, int32_t field, double out[4]);
 
 /* Kernel timing with HIP events recorded on the grid's stream around each
  * launch of the named kernel family ("rhs", "details", "ghost_refine",
- * "ghost_restrict").  mr_prof_enable(g, 1) clears and starts recording;
+ * "ghost_subst", "ghost_restrict").  mr_prof_enable(g, 1) clears and starts recording;
  * mr_prof_read synchronises and returns the summed milliseconds, the number
  * of launches and the points processed per launch.  The names
  * "adapt_criterion", "adapt_plan", "adapt_apply" and "tree_commit" return
@@ -221,8 +246,13 @@ mr_status mr_prof_read(mr_grid* g, const char* kernel, double* total_ms, int64_t
  * produced per stencil-depth reconstruction, out[2] = substitution work
  * items, out[3] = finest level, out[4] = coarsest level, out[5] = refinement
  * work items, out[6] = restriction work items, out[7] / out[8] = their LDS
- * bytes, out[9] = allocated patch values. */
-mr_status mr_tree_stats(const mr_grid* g, int64_t out[10]);
+ * bytes, out[9] = allocated patch values; per stencil-depth reconstruction,
+ * the values each launch must write and read: out[10] / out[11] = c->f patch
+ * values / coarse samples, out[12] / out[13] = substituted points / staged
+ * points, out[14] / out[15] = f->c patch values / fine window points;
+ * out[16..21] = the same six counts for the wide reconstruction of the
+ * detail pass. */
+mr_status mr_tree_stats(const mr_grid* g, int64_t out[22]);
 
 /* Wait until all work issued on the grid's stream has finished. */
 mr_status mr_sync(mr_grid* g);

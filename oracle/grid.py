@@ -457,21 +457,27 @@ class Grid:
         coefficients on the block's own positions [0, nb)^3."""
         f, b = transform_reach(self.N, self.Nt)
         D = max(f, b)
-        X = self.ghost_block(key, D)
+        return self.transform_of(self.ghost_block(key, D), D)
+
+    def transform_of(self, X, D):
+        """The transform of block_transform applied to a given ghost-filled
+        block X of depth D (array [z, y, x] of (nb + 2D)^3 values)."""
         nb = self.nb
         T = wv.analysis(X, 2, -D, 0, nb, self.N, self.Nt)
         T = wv.analysis(T, 1, -D, 0, nb, self.N, self.Nt)
         T = wv.analysis(T, 0, -D, 0, nb, self.N, self.Nt)
         return T
 
-    def block_details(self, key):
-        """Detail coefficients (points with at least one odd index) of the
-        block, zero at the scaling (all-even) positions."""
-        T = self.block_transform(key)
-        nb = self.nb
-        idx = np.arange(nb) % 2
+    def details_of(self, T):
+        """Detail coefficients (points with at least one odd index) of a
+        block transform T, zero at the scaling (all-even) positions."""
+        idx = np.arange(self.nb) % 2
         odd = (idx[:, None, None] + idx[None, :, None] + idx[None, None, :]) > 0
         return np.where(odd, T, 0.0)
+
+    def block_details(self, key):
+        """Detail coefficients of the block's ghost-filled transform."""
+        return self.details_of(self.block_transform(key))
 
     def block_norm(self, key, det=None):
         """Block criterion of section 2.2.5 for one block: max |gamma^{L-1}|

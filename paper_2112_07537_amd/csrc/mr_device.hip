@@ -506,40 +506,6 @@ __device__ __forceinline__ void make_desc(const DevGrid<T>& g, int b, int r, Des
 }
 
 // ------------------------------------------------------------ substitution
-// Slab membership (sections 2.2.2, 2.2.4): point (x, y, z) of a fine block
-// whose regions with a coarser owner are the set bits of cmask (bit r =
-// region rx + 3 ry + 9 rz).  Facing a coarser region in direction d, the
-// slab spans [0, FL) on axes with d = -1 and [BL, NB) on axes with d = +1;
-// lifted, it takes every point with an odd index; unlifted, the points even
-// on the facing axes and odd on a tangential one.
-template <int N, int NT, int NB>
-__device__ __forceinline__ bool in_slabs(int cmask, int x, int y, int z) {
-  constexpr int FL = NT ? N : N - 1;
-  constexpr int BL = NT ? NB - N + 1 : NB - N + 2;
-  const int px = x & 1, py = y & 1, pz = z & 1;
-  if (NT && (px | py | pz) == 0) return false;
-  const int lx = x < FL, hx = x >= BL, ly = y < FL, hy = y >= BL, lz = z < FL, hz = z >= BL;
-#pragma unroll
-  for (int dz = -1; dz <= 1; ++dz) {
-    if ((dz < 0 && !lz) || (dz > 0 && !hz)) continue;
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-      if ((dy < 0 && !ly) || (dy > 0 && !hy)) continue;
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        if ((dx < 0 && !lx) || (dx > 0 && !hx)) continue;
-        if (dx == 0 && dy == 0 && dz == 0) continue;
-        if (!((cmask >> ((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1))) & 1)) continue;
-        if (NT) return true;
-        const bool even_facing = (dx == 0 || !px) && (dy == 0 || !py) && (dz == 0 || !pz);
-        const bool odd_tang = (dx == 0 && px) || (dy == 0 && py) || (dz == 0 && pz);
-        if (even_facing && odd_tang) return true;
-      }
-    }
-  }
-  return false;
-}
-
 // New value of a point of parity (PX, PY, PZ) (section 2.3, 1D sign of
 // section 2.2.4): minus the non-central taps of the tensor product of G^a
 // over its odd axes, read from the staged region V around element i.  The
@@ -548,7 +514,10 @@ __device__ __forceinline__ bool in_slabs(int cmask, int x, int y, int z) {
 template <typename T, int N, int PX, int PY, int PZ>
 __device__ __forceinline__ T subst_point(const T* V, int i, int sy, int sz) {
   constexpr int RX = PX ? N - 1 : 0, RY = PY ? N - 1 : 0, RZ = PZ ? N - 1 : 0;
-  T acc = T(0);
+  // four partial sums (taps in a fixed round-robin order) shorten the
+  // dependent chain; they are added in a fixed order too
+  T acc[4] = {T(0), T(0), T(0), T(0)};
+  int k = 0;
 #pragma unroll
   for (int oz = -RZ; oz <= RZ; ++oz) {
     if (oz != 0 && !(oz & 1)) continue;
@@ -562,23 +531,39 @@ __device__ __forceinline__ T subst_point(const T* V, int i, int sy, int sz) {
         constexpr double one = 1.0;
         const double w = (PZ ? Ga<N>::c(oz) : one) * (PY ? Ga<N>::c(oy) : one) *
                          (PX ? Ga<N>::c(ox) : one);
-        acc += T(w) * V[i + ox + oy * sy + oz * sz];
+        acc[k & 3] += T(w) * V[i + ox + oy * sy + oz * sz];
+        ++k;
       }
     }
   }
-  return -acc;
+  return -((acc[0] + acc[1]) + (acc[2] + acc[3]));
 }
 
-template <typename T, int N>
-__device__ __forceinline__ T subst_any(const T* V, int i, int par, int sy, int sz) {
-  switch (par) {
-    case 1: return subst_point<T, N, 1, 0, 0>(V, i, sy, sz);
-    case 2: return subst_point<T, N, 0, 1, 0>(V, i, sy, sz);
-    case 4: return subst_point<T, N, 0, 0, 1>(V, i, sy, sz);
-    case 3: return subst_point<T, N, 1, 1, 0>(V, i, sy, sz);
-    case 5: return subst_point<T, N, 1, 0, 1>(V, i, sy, sz);
-    case 6: return subst_point<T, N, 0, 1, 1>(V, i, sy, sz);
-    default: return subst_point<T, N, 1, 1, 1>(V, i, sy, sz);
+// Lattice coordinates of a substitution item along each axis, split by
+// parity: all staged coordinates (lat) and those inside the box (box), as
+// offsets in the staged region.
+struct SubstLattice {
+  int8_t lat[3][2][40];
+  int8_t box[3][2][40];
+  int32_t nlat[3][2], nbox[3][2];
+};
+
+// Runs fn(li, x, y, z) over the points of one parity class (PX, PY, PZ) of
+// the staged lattice (BOX = false) or of the box (BOX = true); all lanes of
+// a wave work on points of the same class.
+template <int PX, int PY, int PZ, bool BOX, typename Fn>
+__device__ __forceinline__ void for_class(const SubstLattice& L, const int* r0, const int* rs, Fn fn) {
+  const int n0 = BOX ? L.nbox[0][PX] : L.nlat[0][PX];
+  const int n1 = BOX ? L.nbox[1][PY] : L.nlat[1][PY];
+  const int n2 = BOX ? L.nbox[2][PZ] : L.nlat[2][PZ];
+  const int n = n0 * n1 * n2;
+  if (n == 0) return;
+  Iter3 q(threadIdx.x, blockDim.x, n0, n1);
+  for (int i = threadIdx.x; i < n; i += blockDim.x, q.advance()) {
+    const int qx = BOX ? L.box[0][PX][q.x] : L.lat[0][PX][q.x];
+    const int qy = BOX ? L.box[1][PY][q.y] : L.lat[1][PY][q.y];
+    const int qz = BOX ? L.box[2][PZ][q.z] : L.lat[2][PZ][q.z];
+    fn((qz * rs[1] + qy) * rs[0] + qx, r0[0] + qx, r0[1] + qy, r0[2] + qz);
   }
 }
 
@@ -589,11 +574,15 @@ __device__ __forceinline__ T subst_any(const T* V, int i, int par, int sy, int s
 // the refinement of the samples from before the substitution (the patch
 // launch runs first).  A box point's chain of stencils (degree 3 -> 2 -> 1
 // -> 0, one axis per step) only reads points whose coordinate on every axis
-// lies in the box or is even, so only those are staged.  Then, degree 1 and
-// then degree 2, every slab point of F in the staged region whose stencil
-// lies inside it is replaced in LDS; finally the box's slab points (degree 3
-// computed last) are written to the field.  With 26-neighbour 2:1 balance no
-// finer region lies within the widened box of a slab.
+// lies in the box or is even (the lattice), so only those are staged, each
+// with its slab flag from the owning block's slab table (host-built per
+// block: bit lo | hi << 3 | parity << 6 set when a point with that front /
+// back slab range membership and parity lies in one of the block's slabs).
+// Then, degree 1 and then degree 2, every flagged lattice point is replaced
+// in LDS; finally the box's flagged points (degree 3 computed last) are
+// written to the field.  A staged point's odd coordinates lie in the box, so
+// its stencil stays inside the staged region.  With 26-neighbour 2:1 balance
+// no finer region lies within the widened box of a slab.
 //
 // Items run in any order and each writes only its own box (the host cuts a
 // block's slabs into disjoint boxes), but reads points of other boxes, its
@@ -604,88 +593,136 @@ __device__ __forceinline__ T subst_any(const T* V, int i, int par, int sy, int s
 // slab value was read before or after its own item wrote it never matters,
 // and the result does not depend on the order of the items.
 template <typename T, int N, int NT, int NB>
-__global__ __launch_bounds__(256) void k_subst(DevGrid<T> g, const GItem* __restrict__ items) {
+__global__ __launch_bounds__(512) void k_subst(DevGrid<T> g, const GItem* __restrict__ items) {
   extern __shared__ unsigned char lds_raw[];
   T* V = reinterpret_cast<T*>(lds_raw);
   __shared__ Desc desc[27];
-  __shared__ int32_t cd[27];   // coarser-region mask of the block owning each
-                               // region at F's level, -1 for other levels
+  __shared__ uint64_t tab[27][8];   // slab tables of the blocks owning the
+                                    // regions at F's level (zero otherwise)
+  __shared__ SubstLattice L;
+  __shared__ int8_t latall[3][40];  // all lattice coordinates per axis
+  __shared__ int32_t nall[3];
   constexpr int R = N - 1;
+  constexpr int FL = NT ? N : N - 1;        // front slab [0, FL)
+  constexpr int BL = NT ? NB - N + 1 : NB - N + 2;   // back slab [BL, NB)
   const GItem it = items[xcd_item(blockIdx.x, gridDim.x)];
   const int F = it.blk;
   const int tid = threadIdx.x, nt = blockDim.x;
-  if (tid < 27) {
-    make_desc(g, F, tid, desc[tid]);
-    const int rx = tid % 3, ry = (tid / 3) % 3, rz = tid / 9;
+  if (tid < 27) make_desc(g, F, tid, desc[tid]);
+  if (tid < 27 * 8) {
+    const int r = tid >> 3, w = tid & 7;
+    const int rx = r % 3, ry = (r / 3) % 3, rz = r / 9;
     const int cx = rx == 0 ? 0 : (rx == 1 ? 1 : 3);
     const int cy = ry == 0 ? 0 : (ry == 1 ? 1 : 3);
     const int cz = rz == 0 ? 0 : (rz == 1 ? 1 : 3);
-    const int o = g.cmap[F * 64 + (cz * 4 + cy) * 4 + cx];
-    cd[tid] = (tid == 13) ? g.cdir[F] : (g.poff[(int64_t)F * 27 + tid] < 0 ? g.cdir[o] : -1);
+    const int o = r == 13 ? F : g.cmap[F * 64 + (cz * 4 + cy) * 4 + cx];
+    const bool same = r == 13 || g.poff[(int64_t)F * 27 + r] < 0;
+    tab[r][w] = same ? g.stab[(int64_t)o * 8 + w] : 0ull;
   }
-  // slab membership of a staged point, in the frame of the block owning it
-  auto in_s = [&](int x, int y, int z) -> bool {
-    const int rx = x < 0 ? 0 : (x < NB ? 1 : 2);
-    const int ry = y < 0 ? 0 : (y < NB ? 1 : 2);
-    const int rz = z < 0 ? 0 : (z < NB ? 1 : 2);
-    const int m = cd[rx + 3 * ry + 9 * rz];
-    return m > 0 && in_slabs<N, NT, NB>(m, x - (rx - 1) * NB, y - (ry - 1) * NB, z - (rz - 1) * NB);
-  };
   int r0[3], rs[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     r0[a] = it.lo[a] - R;
     rs[a] = it.hi[a] - it.lo[a] + 2 * R;
   }
+  if (tid < 3) {
+    const int a = tid;
+    const int lo = a == 0 ? it.lo[0] : (a == 1 ? it.lo[1] : it.lo[2]);
+    const int hi = a == 0 ? it.hi[0] : (a == 1 ? it.hi[1] : it.hi[2]);
+    int c[2] = {0, 0}, cb[2] = {0, 0}, ca = 0;
+    for (int v = lo - R; v < hi + R; ++v) {
+      const bool inb = v >= lo && v < hi;
+      const int p = v & 1;
+      const int8_t q = int8_t(v - (lo - R));
+      if (inb || !p) {
+        L.lat[a][p][c[p]++] = q;
+        latall[a][ca++] = q;
+      }
+      if (inb) L.box[a][p][cb[p]++] = q;
+    }
+    for (int p = 0; p < 2; ++p) {
+      L.nlat[a][p] = c[p];
+      L.nbox[a][p] = cb[p];
+    }
+    nall[a] = ca;
+  }
   const int sy = rs[0], sz = rs[0] * rs[1];
-  const int n = sz * rs[2];
+  uint8_t* FLG = reinterpret_cast<uint8_t*>(V + (size_t)sz * rs[2]);
   __syncthreads();
   {
-    Iter3 q(tid, nt, rs[0], rs[1]);
-    for (int i = tid; i < n; i += nt, q.advance()) {
-      const int x = r0[0] + q.x, y = r0[1] + q.y, z = r0[2] + q.z;
-      const bool lat = (!(x & 1) || (x >= it.lo[0] && x < it.hi[0])) &&
-                       (!(y & 1) || (y >= it.lo[1] && y < it.hi[1])) &&
-                       (!(z & 1) || (z >= it.lo[2] && z < it.hi[2]));
-      if (!lat) continue;
-      const int rx = x < 0 ? 0 : (x < NB ? 1 : 2);
-      const int ry = y < 0 ? 0 : (y < NB ? 1 : 2);
-      const int rz = z < 0 ? 0 : (z < NB ? 1 : 2);
-      const Desc d = desc[rx + 3 * ry + 9 * rz];
-      V[i] = (d.patch ? g.patch : g.field)[d.off + x + (int64_t)y * d.sy + (int64_t)z * d.sz];
+    // stage the lattice, value and slab flag; U loads in flight per thread
+    constexpr int U = 8;
+    const int l0 = nall[0], l1 = nall[1], nl = l0 * l1 * nall[2];
+    Iter3 q(tid, nt, l0, l1);
+    for (int i0 = tid; i0 < nl; i0 += U * nt) {
+      T v[U];
+      int li[U];
+      uint8_t fl[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool in = i0 + u * nt < nl;
+        const int qx = latall[0][in ? q.x : 0], qy = latall[1][in ? q.y : 0],
+                  qz = latall[2][in ? q.z : 0];
+        const int x = r0[0] + qx, y = r0[1] + qy, z = r0[2] + qz;
+        const int rx = x < 0 ? 0 : (x < NB ? 1 : 2);
+        const int ry = y < 0 ? 0 : (y < NB ? 1 : 2);
+        const int rz = z < 0 ? 0 : (z < NB ? 1 : 2);
+        const int r = rx + 3 * ry + 9 * rz;
+        const Desc d = desc[r];
+        v[u] = (d.patch ? g.patch : g.field)[d.off + x + (int64_t)y * d.sy + (int64_t)z * d.sz];
+        li[u] = (qz * rs[1] + qy) * rs[0] + qx;
+        const int lx = x - (rx - 1) * NB, ly = y - (ry - 1) * NB, lz = z - (rz - 1) * NB;
+        const int bits = (lx < FL) | ((ly < FL) << 1) | ((lz < FL) << 2) | ((lx >= BL) << 3) |
+                         ((ly >= BL) << 4) | ((lz >= BL) << 5) |
+                         (((x & 1) | ((y & 1) << 1) | ((z & 1) << 2)) << 6);
+        fl[u] = uint8_t((tab[r][bits >> 6] >> (bits & 63)) & 1);
+        q.advance();
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * nt < nl) {
+          V[li[u]] = v[u];
+          FLG[li[u]] = fl[u];
+        }
     }
   }
   __syncthreads();
-  // degrees 1 and 2 over the staged region, in place: degree k reads only
-  // points of lower degree
-#pragma unroll 1
-  for (int deg = 1; deg <= 2; ++deg) {
-    Iter3 q(tid, nt, rs[0], rs[1]);
-    for (int i = tid; i < n; i += nt, q.advance()) {
-      const int x = r0[0] + q.x, y = r0[1] + q.y, z = r0[2] + q.z;
-      const int px = x & 1, py = y & 1, pz = z & 1;
-      if (px + py + pz != deg) continue;
-      if ((px && (q.x < R || q.x >= rs[0] - R)) || (py && (q.y < R || q.y >= rs[1] - R)) ||
-          (pz && (q.z < R || q.z >= rs[2] - R)))
-        continue;
-      if (!in_s(x, y, z)) continue;
-      V[i] = subst_any<T, N>(V, i, px | (py << 1) | (pz << 2), sy, sz);
-    }
-    __syncthreads();
-  }
-  {
-    const int b0 = it.hi[0] - it.lo[0], b1 = it.hi[1] - it.lo[1];
-    const int bn = b0 * b1 * (it.hi[2] - it.lo[2]);
-    T* fb = g.field + (int64_t)F * (NB * NB * NB);
-    Iter3 q(tid, nt, b0, b1);
-    for (int i = tid; i < bn; i += nt, q.advance()) {
-      const int x = it.lo[0] + q.x, y = it.lo[1] + q.y, z = it.lo[2] + q.z;
-      const int par = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
-      if (!par || !in_slabs<N, NT, NB>(cd[13], x, y, z)) continue;
-      const int li = ((q.z + R) * rs[1] + (q.y + R)) * rs[0] + (q.x + R);
-      fb[(z * NB + y) * NB + x] = par == 7 ? subst_point<T, N, 1, 1, 1>(V, li, sy, sz) : V[li];
-    }
-  }
+  // degree 1, then degree 2, over the staged lattice, in place: degree k
+  // reads only points of lower degree
+  for_class<1, 0, 0, false>(L, r0, rs, [&](int li, int, int, int) {
+    if (FLG[li]) V[li] = subst_point<T, N, 1, 0, 0>(V, li, sy, sz);
+  });
+  for_class<0, 1, 0, false>(L, r0, rs, [&](int li, int, int, int) {
+    if (FLG[li]) V[li] = subst_point<T, N, 0, 1, 0>(V, li, sy, sz);
+  });
+  for_class<0, 0, 1, false>(L, r0, rs, [&](int li, int, int, int) {
+    if (FLG[li]) V[li] = subst_point<T, N, 0, 0, 1>(V, li, sy, sz);
+  });
+  __syncthreads();
+  for_class<1, 1, 0, false>(L, r0, rs, [&](int li, int, int, int) {
+    if (FLG[li]) V[li] = subst_point<T, N, 1, 1, 0>(V, li, sy, sz);
+  });
+  for_class<1, 0, 1, false>(L, r0, rs, [&](int li, int, int, int) {
+    if (FLG[li]) V[li] = subst_point<T, N, 1, 0, 1>(V, li, sy, sz);
+  });
+  for_class<0, 1, 1, false>(L, r0, rs, [&](int li, int, int, int) {
+    if (FLG[li]) V[li] = subst_point<T, N, 0, 1, 1>(V, li, sy, sz);
+  });
+  __syncthreads();
+  // the box's slab points to the field, degree 3 computed here
+  T* fb = g.field + (int64_t)F * (NB * NB * NB);
+  auto put = [&](int li, int x, int y, int z) {
+    if (FLG[li]) fb[(z * NB + y) * NB + x] = V[li];
+  };
+  for_class<1, 0, 0, true>(L, r0, rs, put);
+  for_class<0, 1, 0, true>(L, r0, rs, put);
+  for_class<0, 0, 1, true>(L, r0, rs, put);
+  for_class<1, 1, 0, true>(L, r0, rs, put);
+  for_class<1, 0, 1, true>(L, r0, rs, put);
+  for_class<0, 1, 1, true>(L, r0, rs, put);
+  for_class<1, 1, 1, true>(L, r0, rs, [&](int li, int x, int y, int z) {
+    if (FLG[li]) fb[(z * NB + y) * NB + x] = subst_point<T, N, 1, 1, 1>(V, li, sy, sz);
+  });
 }
 
 // ------------------------------------------------------ restriction (f->c)
@@ -1531,7 +1568,7 @@ void launch_gview(bool f32, const void* dg, Wavelet w, const GItem* items, int n
 
 template <typename T, int NB>
 static void subst_nb(const DevGrid<T>& g, Wavelet w, const GItem* items, int n, int lds, hipStream_t s) {
-  MR_WAVELET_SWITCH(w, MR_LAUNCH((k_subst<T, N_, NT_, NB>), dim3(n), dim3(256), lds, s, g, items));
+  MR_WAVELET_SWITCH(w, MR_LAUNCH((k_subst<T, N_, NT_, NB>), dim3(n), dim3(512), lds, s, g, items));
 }
 template <typename T>
 static void subst_t(const void* dg, Wavelet w, const GItem* items, int n, int lds, hipStream_t s) {

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -97,11 +98,15 @@ struct LeafIndex {
   }
 };
 
+// Device buffer: library-owned (hipMalloc, grow on demand) or a fixed slice
+// of a caller-owned pool (never freed or grown by the library).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool owned = true;
   hipError_t ensure(size_t n) {
     if (n <= bytes && p) return hipSuccess;
+    if (!owned) return hipErrorOutOfMemory;
     if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
@@ -110,10 +115,16 @@ struct DevBuf {
     if (e == hipSuccess) bytes = want;
     return e;
   }
+  void adopt(void* q, size_t n) {
+    p = q;
+    bytes = n;
+    owned = false;
+  }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    owned = true;
   }
 };
 
@@ -127,6 +138,10 @@ struct Lists {
   int rcls[4] = {0, 0, 0, 0};
   int lds_rc[3] = {0, 0, 0};
   int64_t out_points = 0;
+  // values each launch of the reconstruction writes and reads (the
+  // algorithmic traffic of the lists): c->f patch values / coarse samples,
+  // substituted points / staged points, f->c values / fine window points
+  int64_t cf_w = 0, cf_r = 0, sb_w = 0, sb_r = 0, fc_w = 0, fc_r = 0;
   DevBuf dg, ds, dr;
 };
 
@@ -171,6 +186,7 @@ struct mr_grid {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   HostTimer htime;
   DevBuf ad_pairs, ad_items, ad_scr, ad_det, ad_slot;   // adaptation scratch
+  std::vector<DevBuf> backup;   // fields at the start of an mr_adapt call
   bool f32 = false;
   int nb = 16, N = 4, Nt = 0, G = 2, Dw = 4;
   int Ef = 0, Eb = 0;
@@ -180,11 +196,13 @@ struct mr_grid {
   LeafIndex index;
   std::vector<int32_t> cmap;
   std::vector<int64_t> poff;
+  std::vector<int32_t> cdir_host;   // per block: bit r = region r is coarser
+  std::vector<uint64_t> stab_host;  // per block: 512-bit slab table (8 words)
   int64_t patch_elems = 0;
   // device
   std::vector<DevBuf> fields, alts;
   DevBuf tmpA, tmpB;
-  DevBuf d_lev, d_ijk, d_cmap, d_poff, d_patch, d_err, d_cbase, d_cstep, d_cdir;
+  DevBuf d_lev, d_ijk, d_cmap, d_poff, d_patch, d_err, d_cbase, d_cstep, d_stab;
   // second patch buffer of the same layout, for the later stages of a fused
   // step while the detail pass still reads the first (allocated on demand)
   DevBuf d_patch2;
@@ -407,11 +425,12 @@ static int rview_lds(const RItem& it, int H, size_t esz) {
 // values do not depend on the tiling, and the f->c tiling is fixed.
 static const int kLdsBudgetRefine = 20 * 1024;
 static const int kLdsBudgetRestrict = 24 * 1024;
-static const int kLdsBudgetSubst = 32 * 1024;
+static const int kLdsBudgetSubst = 60 * 1024;
 
-// LDS of a substitution item: its box widened by N-1 points on every axis.
+// LDS of a substitution item: its box widened by N-1 points on every axis,
+// one value and one flag byte per point.
 static int subst_lds(const GItem& it, int N, size_t esz) {
-  size_t v = esz;
+  size_t v = esz + 1;
   for (int a = 0; a < 3; ++a) v *= size_t(it.hi[a] - it.lo[a] + 2 * (N - 1));
   return int(v);
 }
@@ -654,6 +673,64 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
       if (cs > 32) return fail(MR_EINVAL, "refinement item too wide");
     }
   }
+  // algorithmic traffic of the lists (values per reconstruction)
+  L.cf_w = L.cf_r = L.sb_w = L.sb_r = L.fc_w = L.fc_r = 0;
+  for (const GItem& it : L.g) {
+    int64_t r = 1;
+    for (int a = 0; a < 3; ++a) {
+      int clo, cs;
+      gview_samples(it.lo[a], it.hi[a], N, &clo, &cs);
+      r *= cs;
+    }
+    L.cf_r += r;
+    for (int rr = 0; rr < 27; ++rr) {
+      if (!((it.rmask >> rr) & 1)) continue;
+      int blo[3], bhi[3];
+      region_box(nb, Dc, rr, blo, bhi);
+      int64_t v = 1;
+      for (int a = 0; a < 3; ++a) v *= std::max(0, std::min(bhi[a], it.hi[a]) - std::max(blo[a], it.lo[a]));
+      L.cf_w += v;
+    }
+  }
+  {
+    // slab points (the kernel's selector) and staged lattice points per item
+    const int FL = Nt ? N : N - 1, BL = Nt ? nb - N + 1 : nb - N + 2;
+    for (const GItem& it : L.s) {
+      int64_t vol = 1, ev = 1, lat = 1;
+      for (int a = 0; a < 3; ++a) {
+        const int lo = it.lo[a], hi = it.hi[a];
+        vol *= hi - lo;
+        ev *= (hi - lo + (lo & 1 ? 0 : 1)) / 2;
+        int c = 0;
+        for (int v = lo - (N - 1); v < hi + (N - 1); ++v) c += (v >= lo && v < hi) || !(v & 1);
+        lat *= c;
+      }
+      L.sb_r += lat;
+      if (Nt) {
+        L.sb_w += vol - ev;   // lifted: every point of the slabs but the all-even ones
+        continue;
+      }
+      const uint64_t* t = &g->stab_host[size_t(it.blk) * 8];
+      for (int z = it.lo[2]; z < it.hi[2]; ++z)
+        for (int y = it.lo[1]; y < it.hi[1]; ++y)
+          for (int x = it.lo[0]; x < it.hi[0]; ++x) {
+            const int idx = (x < FL) | ((y < FL) << 1) | ((z < FL) << 2) | ((x >= BL) << 3) |
+                            ((y >= BL) << 4) | ((z >= BL) << 5) |
+                            (((x & 1) | ((y & 1) << 1) | ((z & 1) << 2)) << 6);
+            L.sb_w += (t[idx >> 6] >> (idx & 63)) & 1;
+          }
+    }
+  }
+  for (const RItem& it : L.r) {
+    int64_t w = 1, r = 1;
+    for (int a = 0; a < 3; ++a) {
+      const int q = it.hi[a] - it.lo[a];
+      w *= q;
+      r *= 2 * (q - 1) + 1 + 2 * H;
+    }
+    L.fc_w += w;
+    L.fc_r += r;
+  }
   L.lds_g = 0;
   for (const GItem& it : L.g) L.lds_g = std::max(L.lds_g, gview_lds(it, N, esz));
   L.lds_s = 0;
@@ -735,7 +812,9 @@ static mr_status commit_tree_impl(mr_grid* g) {
       if (g->poff[size_t(b) * 27 + r] >= 0) g->poff[size_t(b) * 27 + r] += base;
   }
   g->patch_elems = cur;
-  std::vector<int32_t> lev(n), ijk(3 * size_t(n)), cdir(n);
+  std::vector<int32_t> lev(n), ijk(3 * size_t(n));
+  std::vector<int32_t>& cdir = g->cdir_host;
+  cdir.assign(n, 0);
   parallel_for(size_t(n), [&](size_t lo_b, size_t hi_b) {
     for (size_t b = lo_b; b < hi_b; ++b) {
       int32_t m = 0;
@@ -744,6 +823,44 @@ static mr_status commit_tree_impl(mr_grid* g) {
       cdir[b] = m;
     }
   });
+  // slab tables (READING R-SUB): bit (lo | hi << 3 | parity << 6) of a block
+  // is set when a point whose per-axis front / back slab range membership is
+  // lo / hi and whose index parities are `parity` lies in one of the slabs
+  // of the block's coarser regions and passes that slab's selector; built
+  // once per distinct mask
+  {
+    std::unordered_map<int32_t, std::array<uint64_t, 8>> memo;
+    auto table = [&](int32_t m) {
+      std::array<uint64_t, 8> t{};
+      for (int idx = 0; idx < 512; ++idx) {
+        const int lo = idx & 7, hi = (idx >> 3) & 7, par = idx >> 6;
+        bool in = false;
+        for (int r = 0; r < 27 && !in; ++r) {
+          if (r == 13 || !((m >> r) & 1)) continue;
+          const int d[3] = {r % 3 - 1, (r / 3) % 3 - 1, r / 9 - 1};
+          bool ok = true, even_facing = true, odd_tang = false;
+          for (int a = 0; a < 3; ++a) {
+            if (d[a] < 0 && !((lo >> a) & 1)) ok = false;
+            if (d[a] > 0 && !((hi >> a) & 1)) ok = false;
+            if (d[a] != 0 && ((par >> a) & 1)) even_facing = false;
+            if (d[a] == 0 && ((par >> a) & 1)) odd_tang = true;
+          }
+          in = ok && (g->Nt ? par != 0 : (even_facing && odd_tang));
+        }
+        if (in) t[idx >> 6] |= 1ull << (idx & 63);
+      }
+      return t;
+    };
+    for (int b = 0; b < n; ++b)
+      if (!memo.count(cdir[b])) memo.emplace(cdir[b], table(cdir[b]));
+    g->stab_host.assign(size_t(n) * 8, 0);
+    parallel_for(size_t(n), [&](size_t lo_b, size_t hi_b) {
+      for (size_t b = lo_b; b < hi_b; ++b) {
+        const auto& t = memo.at(cdir[b]);
+        for (int w = 0; w < 8; ++w) g->stab_host[b * 8 + w] = t[w];
+      }
+    });
+  }
   for (int b = 0; b < n; ++b) {
     lev[b] = g->leaves[b].L;
     ijk[3 * b] = g->leaves[b].i;
@@ -754,7 +871,7 @@ static mr_status commit_tree_impl(mr_grid* g) {
   HIPCHK(g->d_ijk.ensure(std::max(1, 3 * n) * sizeof(int32_t)));
   HIPCHK(g->d_cmap.ensure(std::max(1, 64 * n) * sizeof(int32_t)));
   HIPCHK(g->d_poff.ensure(std::max(1, 27 * n) * sizeof(int64_t)));
-  HIPCHK(g->d_cdir.ensure(std::max(1, n) * sizeof(int32_t)));
+  HIPCHK(g->d_stab.ensure(std::max(1, n) * 8 * sizeof(uint64_t)));
   HIPCHK(g->d_patch.ensure(std::max<int64_t>(1, cur) * g->esz));
   HIPCHK(g->d_bands.ensure(std::max(1, 27 * n) * sizeof(double)));
   HIPCHK(g->d_norms.ensure(std::max(1, n) * sizeof(double)));
@@ -763,7 +880,7 @@ static mr_status commit_tree_impl(mr_grid* g) {
     HIPCHK(hipMemcpyAsync(g->d_ijk.p, ijk.data(), 3 * n * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
     HIPCHK(hipMemcpyAsync(g->d_cmap.p, g->cmap.data(), 64 * size_t(n) * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
     HIPCHK(hipMemcpyAsync(g->d_poff.p, g->poff.data(), 27 * size_t(n) * sizeof(int64_t), hipMemcpyHostToDevice, g->stream));
-    HIPCHK(hipMemcpyAsync(g->d_cdir.p, cdir.data(), size_t(n) * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
+    HIPCHK(hipMemcpyAsync(g->d_stab.p, g->stab_host.data(), size_t(n) * 8 * sizeof(uint64_t), hipMemcpyHostToDevice, g->stream));
     HIPCHK(g->d_cbase.ensure(64 * size_t(n) * sizeof(int64_t)));
     HIPCHK(g->d_cstep.ensure(64 * size_t(n) * sizeof(int32_t)));
     build_cell_tables(g);
@@ -786,7 +903,7 @@ static DevGrid<T> view(mr_grid* g, void* field, void* patch = nullptr) {
   d.ijk = static_cast<const int32_t*>(g->d_ijk.p);
   d.cmap = static_cast<const int32_t*>(g->d_cmap.p);
   d.poff = static_cast<const int64_t*>(g->d_poff.p);
-  d.cdir = static_cast<const int32_t*>(g->d_cdir.p);
+  d.stab = static_cast<const uint64_t*>(g->d_stab.p);
   d.cbase = static_cast<const int64_t*>(g->d_cbase.p);
   d.cstep = static_cast<const int32_t*>(g->d_cstep.p);
   d.field = static_cast<T*>(field);
@@ -1261,10 +1378,9 @@ static mr_status norms_to_host(mr_grid* g, int field, std::vector<double>& out) 
   return MR_OK;
 }
 
-static mr_status adapt_impl(mr_grid* g, int field, int max_iter, mr_adapt_stats* stats) {
+static mr_status adapt_iterations(mr_grid* g, int field, int max_iter, mr_adapt_stats* stats) {
   std::unordered_set<uint64_t> created;
   mr_adapt_stats s{};
-  // an iteration is applied whole or not at all; earlier iterations remain
   HostTimer& ht = g->htime;
   for (int it = 0; it < max_iter; ++it) {
     std::vector<double> norms;
@@ -1298,6 +1414,38 @@ static mr_status adapt_impl(mr_grid* g, int field, int max_iter, mr_adapt_stats*
   s.n_blocks = int64_t(g->leaves.size());
   if (stats) *stats = s;
   return MR_OK;
+}
+
+// mr_adapt is transactional over the whole call: the tree and every field
+// (which the ghost reconstructions of the criterion substitute in place) are
+// saved first; when the call fails with MR_ECAPACITY or MR_ENONFINITE they
+// are restored bit for bit.
+static mr_status adapt_impl(mr_grid* g, int field, int max_iter, mr_adapt_stats* stats) {
+  const std::vector<Key> saved = g->leaves;
+  const size_t bytes = g->leaves.size() * size_t(g->nb) * g->nb * g->nb * g->esz;
+  g->backup.resize(g->cfg.n_fields);
+  for (int f = 0; f < g->cfg.n_fields; ++f) {
+    HIPCHK(g->backup[f].ensure(bytes));
+    HIPCHK(hipMemcpyAsync(g->backup[f].p, g->fields[f].p, bytes, hipMemcpyDeviceToDevice, g->stream));
+  }
+  mr_status st = adapt_iterations(g, field, max_iter, stats);
+  if (st != MR_ECAPACITY && st != MR_ENONFINITE) return st;
+  const std::string msg = g_errmsg;
+  (void)hipStreamSynchronize(g->stream);
+  for (int f = 0; f < g->cfg.n_fields; ++f)
+    HIPCHK(hipMemcpyAsync(g->fields[f].p, g->backup[f].p, bytes, hipMemcpyDeviceToDevice, g->stream));
+  if (g->leaves.size() != saved.size() || !std::equal(saved.begin(), saved.end(), g->leaves.begin(),
+                                                      [](const Key& a, const Key& b) {
+                                                        return a.L == b.L && a.i == b.i &&
+                                                               a.j == b.j && a.k == b.k;
+                                                      })) {
+    g->leaves = saved;
+    mr_status c = commit_tree(g);
+    if (c != MR_OK) return c;
+  }
+  HIPCHK(hipStreamSynchronize(g->stream));
+  g_errmsg = msg;
+  return st;
 }
 
 static mr_status upload_ic(mr_grid* g, int field, const mr_ic* ic) {
@@ -1413,10 +1561,11 @@ static void free_grid(mr_grid* g) {
   }
   for (auto& b : g->fields) b.release();
   for (auto& b : g->alts) b.release();
+  for (auto& b : g->backup) b.release();
   DevBuf* bufs[] = {&g->tmpA, &g->tmpB, &g->d_lev, &g->d_ijk, &g->d_cmap, &g->d_poff, &g->d_patch,
                     &g->d_err, &g->d_bands, &g->d_norms, &g->d_icpar, &g->d_mom,
                     &g->stage.dg, &g->stage.ds, &g->stage.dr, &g->wide.dg, &g->wide.ds,
-                    &g->wide.dr, &g->ad_pairs, &g->d_cbase, &g->d_cstep, &g->d_cdir, &g->d_patch2,
+                    &g->wide.dr, &g->ad_pairs, &g->d_cbase, &g->d_cstep, &g->d_stab, &g->d_patch2,
                     &g->ad_items, &g->ad_scr, &g->ad_det, &g->ad_slot};
   for (DevBuf* b : bufs) b->release();
   if (g->aux) {
@@ -1435,7 +1584,25 @@ extern "C" {
 
 const char* mr_last_error(void) { return g_errmsg.c_str(); }
 
-mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, mr_grid** out) {
+// Bytes of the fixed-capacity field buffers (fields, their adaptation
+// alternates and two work buffers), each a 256-byte-aligned slice.
+static size_t pool_need(const mr_config& c) {
+  const size_t esz = c.prec == MR_F32 ? 4 : 8;
+  const size_t one = (size_t(c.max_blocks) * c.nb * c.nb * c.nb * esz + 255) / 256 * 256;
+  return one * (2 * size_t(c.n_fields) + 2);
+}
+
+mr_status mr_pool_bytes(const mr_config* cfg, size_t* bytes) {
+  if (!cfg || !bytes) return fail(MR_EINVAL, "null argument");
+  if (cfg->n_fields < 1 || cfg->n_fields > 8 || cfg->max_blocks < 1 ||
+      (cfg->nb != 8 && cfg->nb != 16 && cfg->nb != 24) || (cfg->prec != MR_F64 && cfg->prec != MR_F32))
+    return fail(MR_EINVAL, "invalid configuration");
+  *bytes = pool_need(*cfg);
+  return MR_OK;
+}
+
+mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, void* dev_pool, size_t pool_bytes,
+                         mr_grid** out) {
   if (!cfg || !out) return fail(MR_EINVAL, "null argument");
   const mr_config& c = *cfg;
   if (c.nb != 8 && c.nb != 16 && c.nb != 24) return fail(MR_EINVAL, "nb must be 8, 16 or 24");
@@ -1452,6 +1619,11 @@ mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, mr_grid** out) 
   const int64_t n0 = int64_t(1) << (3 * c.level_min);
   if (c.max_blocks < n0 || c.max_blocks > (int64_t(1) << 31))
     return fail(MR_EINVAL, "max_blocks must hold the level_min tree and fit int32");
+  if (dev_pool && (reinterpret_cast<uintptr_t>(dev_pool) % 256 != 0))
+    return fail(MR_EINVAL, "dev_pool must be 256-byte aligned");
+  if (dev_pool && pool_bytes < pool_need(c))
+    return fail(MR_EINVAL, "dev_pool holds " + std::to_string(pool_bytes) + " bytes, the fields need " +
+                               std::to_string(pool_need(c)) + " (mr_pool_bytes)");
   mr_grid* g = new mr_grid();
   g->cfg = c;
   g->stream = static_cast<hipStream_t>(hip_stream);
@@ -1498,6 +1670,20 @@ mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, mr_grid** out) 
   }
   g->fields.resize(c.n_fields);
   g->alts.resize(c.n_fields);
+  if (dev_pool) {
+    // fixed-capacity field buffers as slices of the caller's pool
+    const size_t one = pool_need(c) / (2 * size_t(c.n_fields) + 2);
+    unsigned char* q = static_cast<unsigned char*>(dev_pool);
+    for (int f = 0; f < c.n_fields; ++f) {
+      g->fields[f].adopt(q, one);
+      q += one;
+      g->alts[f].adopt(q, one);
+      q += one;
+    }
+    g->tmpA.adopt(q, one);
+    q += one;
+    g->tmpB.adopt(q, one);
+  }
   std::string warn;
   if (c.eps_refine / std::max(c.eps_coarsen, 1e-300) <= double(1 << g->N))
     warn = "warning: eps_refine/eps_coarsen <= 2^N may flip-flop (section 2.2.5)";
@@ -1813,7 +1999,7 @@ mr_status mr_sync(mr_grid* g) {
   return check_err(g);
 }
 
-mr_status mr_tree_stats(const mr_grid* g, int64_t out[10]) {
+mr_status mr_tree_stats(const mr_grid* g, int64_t out[22]) {
   if (!g || !out) return fail(MR_EINVAL, "null argument");
   int lo = 99, hi = -1;
   for (const Key& k : g->leaves) {
@@ -1830,6 +2016,18 @@ mr_status mr_tree_stats(const mr_grid* g, int64_t out[10]) {
   out[7] = g->stage.lds_g;
   out[8] = std::max(g->stage.lds_rc[0], std::max(g->stage.lds_rc[1], g->stage.lds_rc[2]));
   out[9] = g->patch_elems;
+  out[10] = g->stage.cf_w;
+  out[11] = g->stage.cf_r;
+  out[12] = g->stage.sb_w;
+  out[13] = g->stage.sb_r;
+  out[14] = g->stage.fc_w;
+  out[15] = g->stage.fc_r;
+  out[16] = g->wide.cf_w;
+  out[17] = g->wide.cf_r;
+  out[18] = g->wide.sb_w;
+  out[19] = g->wide.sb_r;
+  out[20] = g->wide.fc_w;
+  out[21] = g->wide.fc_r;
   return MR_OK;
 }
 

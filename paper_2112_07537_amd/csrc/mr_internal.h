@@ -75,7 +75,7 @@ struct DevGrid {
   const int32_t* cmap;   // [64*nblk] leaf id per half-block cell of the
                          //   4x4x4 cells covering [-nb/2, 3nb/2)^3
   const int64_t* poff;   // [27*nblk] patch offset per region, -1 if none
-  const int32_t* cdir;   // [nblk] bit r set: region r has a coarser owner
+  const uint64_t* stab;  // [8*nblk] slab table of each block (k_subst)
   const int64_t* cbase;  // [64*nblk] coarse-sample address table per cell
   const int32_t* cstep;  //   (see k_cell_tables)
   T* field;              // [nblk * nb^3]

@@ -52,7 +52,8 @@ def load():
     lib = C.CDLL(LIB_PATH)
     P = C.c_void_p
     sig = {
-        "mr_grid_create": [C.POINTER(mr_config), P, C.POINTER(P)],
+        "mr_grid_create": [C.POINTER(mr_config), P, P, C.c_size_t, C.POINTER(P)],
+        "mr_pool_bytes": [C.POINTER(mr_config), C.POINTER(C.c_size_t)],
         "mr_grid_destroy": [P],
         "mr_set_tree": [P, C.c_int64, P, P],
         "mr_sample_ic": [P, C.c_int32, C.POINTER(mr_ic)],
@@ -112,20 +113,37 @@ def velocity(kind, *p):
     return v
 
 
+def make_config(nb, N, Nt, fd_order=4, level_min=0, level_max=12, prec="f64", eps_refine=1e-2,
+                eps_coarsen=1e-4, detail_ext=1, n_fields=1, exec_mode=0, max_blocks=1 << 16):
+    return mr_config(nb, N, Nt, fd_order, level_min, level_max,
+                     MR_F32 if prec in ("f32", MR_F32) else MR_F64, detail_ext, n_fields,
+                     exec_mode, eps_refine, eps_coarsen, max_blocks)
+
+
+def pool_bytes(**kw):
+    """Bytes a caller-owned pool must hold for the configuration (mr_pool_bytes)."""
+    n = C.c_size_t()
+    _check(lib().mr_pool_bytes(C.byref(make_config(**kw)), C.byref(n)))
+    return n.value
+
+
 class Grid:
     """Owning handle of an ``mr_grid``; methods map one-to-one to the C ABI."""
 
     def __init__(self, nb, N, Nt, fd_order=4, level_min=0, level_max=12, prec="f64",
                  eps_refine=1e-2, eps_coarsen=1e-4, detail_ext=1, n_fields=1,
-                 exec_mode=0, max_blocks=1 << 16, stream=None):
-        c = mr_config(nb, N, Nt, fd_order, level_min, level_max,
-                      MR_F32 if prec in ("f32", MR_F32) else MR_F64, detail_ext, n_fields,
-                      exec_mode, eps_refine, eps_coarsen, max_blocks)
+                 exec_mode=0, max_blocks=1 << 16, stream=None, pool=None, pool_bytes=0):
+        """``pool``: device address of caller-owned memory (e.g. the data_ptr()
+        of a torch uint8 CUDA tensor, which the caller keeps alive) holding
+        ``pool_bytes`` >= pool_bytes(cfg) for the field buffers."""
+        c = make_config(nb, N, Nt, fd_order, level_min, level_max, prec, eps_refine,
+                        eps_coarsen, detail_ext, n_fields, exec_mode, max_blocks)
         self.cfg = c
         self.dtype = np.float32 if c.prec == MR_F32 else np.float64
         self.nb = nb
         h = C.c_void_p()
-        _check(lib().mr_grid_create(C.byref(c), C.c_void_p(stream), C.byref(h)))
+        _check(lib().mr_grid_create(C.byref(c), C.c_void_p(stream), C.c_void_p(pool),
+                                    C.c_size_t(pool_bytes), C.byref(h)))
         self.warning = lib().mr_last_error().decode()
         self._h = h
 
@@ -261,6 +279,6 @@ class Grid:
         _check(lib().mr_sync(self._h))
 
     def tree_stats(self):
-        a = np.zeros(10, np.int64)
+        a = np.zeros(22, np.int64)
         _check(lib().mr_tree_stats(self._h, _ptr(a)))
         return a

@@ -156,26 +156,92 @@ def c4():
                 tree=("geometric",))
 
 
-def c5(seed=5, eps_refine=3e-6):
-    """Levels 3..9, 24^3 blocks, 6.2, FD6, FP32, sum of 64 Gaussians with
-    log-uniform widths in [0.005, 0.1], shear velocity, adapt every 5 steps.
-
-    The default refine threshold 3e-6 (coarsen 3e-8) is the tightest at which
-    the FP32 grid keeps its size under time stepping (17,116 leaves, levels
-    3..7, for seed 5); below it FP32 rounding of the samples (about 6e-8 of
-    the local value) produces details above the thresholds and the grid keeps
-    refining, which FP64 runs of the same thresholds do not do."""
+def _c5_gaussians(seed):
     r = SplitMix64(seed)
     cs, ss, aa = [], [], []
     for _ in range(64):
         cs.append(tuple(r.uniform(0.0, 1.0) for _ in range(3)))
         ss.append(math.exp(r.uniform(math.log(0.005), math.log(0.1))))
         aa.append(r.uniform(0.5, 1.0))
-    return dict(name="c5_adaptive_l3-9_nb24_w62_fd6_f32_eps%g" % eps_refine, nb=24, N=6, Nt=2, fd=6,
-                level_min=3, level_max=9, prec="f32", eps_refine=eps_refine,
-                eps_coarsen=eps_refine / 100.0,
-                ic=("gauss", gauss_params(cs, ss, aa)),
-                vel=("shear", ()), cfl=0.5, steps=100, adapt_every=5)
+    return gauss_params(cs, ss, aa)
+
+
+def gaussian_tree(params, lmin=3, lmax=9, nb=24, m=40.0, k=1.45):
+    """Leaves refined around the terms of a Gaussian-sum input: term g
+    (centre c, width sigma) asks for blocks of spacing at most sigma / m,
+    i.e. level L_g = ceil(log2(m / (nb sigma))) clipped to [lmin, lmax], and
+    a block at level L < L_g is split when its periodic distance to c is
+    below k sigma.  Then the tree is 2:1-balanced over the 26-neighbourhood
+    with the periodic wrap.  The defaults give 61,461 leaves on levels 3..9
+    for the 64 terms of the seed-5 draw of c5."""
+    rows = np.asarray(params, dtype=np.float64).reshape(-1, 5)
+    tgt = np.clip(np.ceil(np.log2(m / (nb * rows[:, 3]))), lmin, lmax).astype(int)
+    leaves = {(lmin, i, j, kk) for i in range(1 << lmin) for j in range(1 << lmin)
+              for kk in range(1 << lmin)}
+    for L in range(lmin, lmax):
+        h = 2.0 ** -L
+        cur = np.array(sorted(b[1:] for b in leaves if b[0] == L), dtype=np.int64)
+        if len(cur) == 0:
+            continue
+        lo = cur * h
+        split = np.zeros(len(cur), bool)
+        for (cx, cy, cz, sg, _), Lg in zip(rows, tgt):
+            if Lg <= L:
+                continue
+            d2 = np.zeros(len(cur))
+            for ax, c in enumerate((cx, cy, cz)):
+                t = (c - lo[:, ax]) % 1.0      # centre relative to the block start
+                d2 += np.where(t <= h, 0.0, np.minimum(t - h, 1.0 - t)) ** 2
+            split |= d2 < (k * sg) ** 2
+        for i, j, kk in cur[split].tolist():
+            leaves.remove((L, i, j, kk))
+            for c in range(8):
+                leaves.add((L + 1, 2 * i + (c & 1), 2 * j + ((c >> 1) & 1), 2 * kk + ((c >> 2) & 1)))
+    return balance(leaves)
+
+
+_TREES = {}
+
+
+def tree_of(cfg):
+    """Leaf keys of a prescribed-tree workload (cached per process)."""
+    kind = cfg["tree"][0]
+    if kind not in _TREES:
+        if kind == "geometric":
+            _TREES[kind] = geometric_tree()
+        else:
+            _TREES[kind] = gaussian_tree(cfg["ic"][1])
+    return _TREES[kind]
+
+
+def c5(seed=5):
+    """The large workload: 24^3 blocks, 6.2, FD6, FP32, sum of 64 Gaussians
+    with centres uniform in the periodic cube, log-uniform widths in
+    [0.005, 0.1] and amplitudes in [0.5, 1], shear velocity.  The tree is
+    prescribed by the Gaussians (gaussian_tree: 61,461 leaves on levels 3..9,
+    0.850G points).  Flags use eps_refine 1e-4 / eps_coarsen 1e-6, ratio 100
+    above 2^6, with the coarsening threshold about ten times the FP32
+    rounding of unit data; the adaptation timed every 5 steps starts from
+    the prescribed tree."""
+    p = _c5_gaussians(seed)
+    return dict(name="c5_gausstree_l3-9_nb24_w62_fd6_f32", nb=24, N=6, Nt=2, fd=6,
+                level_min=3, level_max=9, prec="f32", eps_refine=1e-4, eps_coarsen=1e-6,
+                ic=("gauss", p), vel=("shear", ()), cfl=0.5, steps=100, adapt_every=5,
+                tree=("gaussian", seed))
+
+
+def c5_adaptive(seed=5, eps_refine=3e-6):
+    """The same input on a threshold-driven tree (initial refinement and
+    adaptation every 5 steps).  At eps_refine 3e-6 (eps_coarsen 3e-8) the
+    FP32 grid keeps its size under time stepping (17,116 leaves, levels
+    3..7); below it FP32 rounding of the samples (about 6e-8 of the local
+    value) produces details above the thresholds and the grid keeps
+    refining, which FP64 runs of the same thresholds do not do."""
+    p = _c5_gaussians(seed)
+    return dict(name="c5a_adaptive_l3-7_nb24_w62_fd6_f32_eps%g" % eps_refine, nb=24, N=6, Nt=2,
+                fd=6, level_min=3, level_max=9, prec="f32", eps_refine=eps_refine,
+                eps_coarsen=eps_refine / 100.0, ic=("gauss", p), vel=("shear", ()), cfl=0.5,
+                steps=100, adapt_every=5)
 
 
 def ic_function(ic):

@@ -46,7 +46,8 @@ def test_binding_covers_every_symbol():
 
 def test_validation_errors_without_device(lib):
     from paper_2112_07537_amd import mr
-    lib.mr_grid_create.argtypes = [C.POINTER(mr.mr_config), C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.mr_grid_create.argtypes = [C.POINTER(mr.mr_config), C.c_void_p, C.c_void_p, C.c_size_t,
+                                   C.POINTER(C.c_void_p)]
     lib.mr_grid_create.restype = C.c_int32
     lib.mr_last_error.restype = C.c_char_p
     h = C.c_void_p()
@@ -58,10 +59,26 @@ def test_validation_errors_without_device(lib):
                   max_blocks=64)
         kw.update(over)
         c = mr.mr_config(**kw)
-        assert lib.mr_grid_create(C.byref(c), None, C.byref(h)) == mr.MR_EINVAL, over
+        assert lib.mr_grid_create(C.byref(c), None, None, 0, C.byref(h)) == mr.MR_EINVAL, over
         assert lib.mr_last_error()
         assert not h.value
-    assert lib.mr_grid_create(None, None, C.byref(h)) == mr.MR_EINVAL
+    assert lib.mr_grid_create(None, None, None, 0, C.byref(h)) == mr.MR_EINVAL
+    # a caller pool must be aligned and large enough (checked before any device call)
+    ok = dict(nb=16, wavelet_N=4, wavelet_Nt=2, fd_order=4, level_min=0, level_max=4, prec=0,
+              detail_ext=1, n_fields=1, exec_mode=0, eps_refine=1e-3, eps_coarsen=1e-5,
+              max_blocks=64)
+    c = mr.mr_config(**ok)
+    lib.mr_pool_bytes.argtypes = [C.POINTER(mr.mr_config), C.POINTER(C.c_size_t)]
+    lib.mr_pool_bytes.restype = C.c_int32
+    need = C.c_size_t()
+    assert lib.mr_pool_bytes(C.byref(c), C.byref(need)) == mr.MR_OK
+    # fields, alternates and two work buffers of max_blocks blocks each
+    assert need.value == 4 * 64 * 16 ** 3 * 8
+    assert lib.mr_grid_create(C.byref(c), None, C.c_void_p(0x1000), need.value - 1,
+                              C.byref(h)) == mr.MR_EINVAL
+    assert lib.mr_grid_create(C.byref(c), None, C.c_void_p(0x1008), need.value,
+                              C.byref(h)) == mr.MR_EINVAL
+    assert not h.value
     # every entry point rejects a null grid handle
     for name, args in (("mr_ghost", (None, 0, 0)), ("mr_details", (None, 0, None, 1)),
                        ("mr_adapt", (None, 0, 0, None)), ("mr_sync", (None,)),

@@ -1,0 +1,100 @@
+"""The boundary's ownership and failure contracts through the C ABI.
+
+* A caller-owned device pool (a torch uint8 tensor) holds the field buffers:
+  steps, reconstructions and adaptations give the same bits as a grid whose
+  buffers the library allocates, and the pool stays the caller's after
+  mr_grid_destroy.
+* mr_adapt is transactional over the whole call: when an iteration would
+  exceed max_blocks, the tree and the field (which the criterion's ghost
+  reconstruction substituted in place) come back exactly as before the
+  call.
+"""
+import numpy as np
+import pytest
+
+from paper_2112_07537_amd import mr
+from paper_2112_07537_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+IC = ("gauss", wl.gauss_params([(0.31, 0.42, 0.36)], [0.05], [1.0]))
+KW = dict(nb=16, N=4, Nt=2, fd_order=4, level_min=1, level_max=4, eps_refine=1e-3,
+          eps_coarsen=1e-5, max_blocks=2048)
+
+
+def run(g):
+    g.set_tree([(1, i, j, k) for k in range(2) for j in range(2) for i in range(2)])
+    g.sample_ic(*IC)
+    st = g.adapt(max_iter=2)
+    v = mr.velocity("shear")
+    dt = g.cfl_dt(v, 0.5)
+    for _ in range(2):
+        g.rk3_step(dt, v)
+    nrm = g.details()
+    return st.n_blocks, g.block_meta().copy(), g.field_get().copy(), nrm
+
+
+def test_caller_pool_matches_library_allocation():
+    import torch
+    need = mr.pool_bytes(**KW)
+    pool = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    base = pool.data_ptr()
+    base += (-base) % 256
+    with pytest.raises(mr.MRError) as e:
+        mr.Grid(**KW, pool=base, pool_bytes=need - 1)
+    assert e.value.code == mr.MR_EINVAL
+    torch.cuda.synchronize()
+    a = mr.Grid(**KW, pool=base, pool_bytes=need)
+    b = mr.Grid(**KW)
+    ra, rb = run(a), run(b)
+    assert ra[0] == rb[0] and ra[0] > 8
+    for x, y in zip(ra[1:], rb[1:]):
+        assert np.array_equal(x, y)
+    ptr = a.field_ptr()
+    assert base <= ptr < base + need
+    a.close()
+    b.close()
+    # the pool is still the caller's memory
+    pool.fill_(7)
+    torch.cuda.synchronize()
+    assert int(pool[:need].sum().item()) == 7 * need
+
+
+def test_adapt_is_transactional_over_the_call():
+    """Random data on a tree with resolution jumps: the criterion's ghost
+    reconstruction substitutes slab points of the field in place, then the
+    first iteration needs more than max_blocks blocks.  The call fails with
+    MR_ECAPACITY and the field comes back bit for bit (the substitution
+    undone), the tree unchanged."""
+    keys = [(1, i, j, k) for k in range(2) for j in range(2) for i in range(2)
+            if (i, j, k) != (0, 0, 0)]
+    keys += [(2, c & 1, (c >> 1) & 1, (c >> 2) & 1) for c in range(8)]
+    g = mr.Grid(**dict(KW, max_blocks=64))
+    g.set_tree(keys)
+    rng = np.random.default_rng(5)
+    g.field_set(rng.standard_normal((g.n_blocks(), 16, 16, 16)))
+    meta0 = g.block_meta().copy()
+    f0 = g.field_get().copy()
+    # the reconstruction alone does change the field (substitution)
+    probe = mr.Grid(**dict(KW, max_blocks=64))
+    probe.set_tree(keys)
+    probe.field_set(f0)
+    probe.ghost(depth=0)
+    assert not np.array_equal(probe.field_get(), f0)
+    probe.close()
+    with pytest.raises(mr.MRError) as e:
+        g.adapt(max_iter=8)
+    assert e.value.code == mr.MR_ECAPACITY
+    assert np.array_equal(g.block_meta(), meta0)
+    assert np.array_equal(g.field_get(), f0)
+    # the grid is whole: it steps like a fresh grid holding the same state
+    ref = mr.Grid(**dict(KW, max_blocks=64))
+    ref.set_tree(keys)
+    ref.field_set(f0)
+    v = mr.velocity("const", 1.0, 0.5, 0.25)
+    dt = g.cfl_dt(v, 0.5)
+    g.rk3_step(dt, v)
+    ref.rk3_step(dt, v)
+    assert np.array_equal(g.field_get(), ref.field_get())
+    g.close()
+    ref.close()

@@ -2,8 +2,9 @@
 
 * C2 (adaptive levels 2..5, 16^3, 4.2, FP64), C3 (adaptive levels 3..7,
   24^3, 6.2, FD6), C4 (prescribed geometric tree, 21,652 leaves of 16^3, 4.2,
-  FD4) and C5 (adaptive, 24^3 blocks, 6.2, FD6, the benchmark workload) are
-  built on the GPU exactly as bench.py builds them.  For a seeded sample of blocks the ghost-filled blocks (stencil
+  FD4) and C5 (prescribed Gaussian tree, 61,461 leaves of 24^3 on levels
+  3..9, 6.2, FD6, the benchmark workload) are built on the GPU exactly as
+  bench.py builds them.  For a seeded sample of blocks the ghost-filled blocks (stencil
   depth and wide depth) are compared with the FP64 oracle's level view, and
   the detail norms with the oracle's per-block transform.
 * Property at any size: one FP32 RK3 step against one FP64 RK3 step from the
@@ -22,16 +23,13 @@ from paper_2112_07537_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-BENCH_EPS_C5 = 3e-6  # the benchmark default
-
-
 def build(cfg, prec=None, exec_mode=0):
     g = mr.Grid(cfg["nb"], cfg["N"], cfg["Nt"], fd_order=cfg["fd"], level_min=cfg["level_min"],
                 level_max=cfg["level_max"], prec=prec or cfg["prec"],
                 eps_refine=cfg["eps_refine"], eps_coarsen=cfg["eps_coarsen"],
                 exec_mode=exec_mode, max_blocks=150000)
     if cfg.get("tree"):
-        g.set_tree(wl.geometric_tree())
+        g.set_tree(wl.tree_of(cfg))
         g.sample_ic(*cfg["ic"])
     else:
         g.init_ic(*cfg["ic"])
@@ -56,7 +54,6 @@ def wide_depth(cfg):
 @pytest.fixture(scope="module", params=["c2", "c3", "c4", "c5"])
 def fullsize(request):
     cfg = getattr(wl, request.param)()
-    assert request.param != "c5" or cfg["eps_refine"] == BENCH_EPS_C5
     g = build(cfg)
     yield cfg, g
     g.close()
@@ -112,33 +109,49 @@ def test_fullsize_ghost_and_details_sampled(fullsize):
 
 def test_fullsize_flags_sampled(fullsize):
     """Detail norms and refine/coarsen flags of sampled blocks at the bench
-    size, GPU against the FP64 oracle evaluated on the GPU's ghost-filled
-    field.  Norms agree within the FP32 contract (1e-5 of max|phi|); flags
-    agree except for blocks whose oracle norm lies within 1e-4 relative of a
-    threshold or within the FP32 rounding of the ghost values (2e-7 of
-    max|phi|, about three units of FP32 roundoff)."""
+    size.  Each GPU norm is compared with the oracle's FP64 transform of the
+    GPU's own wide-depth ghost-filled blocks (the block and its same-level
+    neighbours, whose bands the norm takes), upcast: 1e-12 relative plus the
+    FP64 rounding of the sums (1e-14 of max|phi|).  Flags (section 2.2.5,
+    refine at >= eps_refine, coarsen at <= eps_coarsen) agree exactly except
+    where the oracle norm lies within 1e-4 relative of a threshold."""
     cfg, g = fullsize
     keys = [tuple(int(v) for v in m) for m in g.block_meta()]
-    nrm = g.details()                      # ghost fill (substitution) + transform
+    index = {k: b for b, k in enumerate(keys)}
+    nrm = g.details()                      # wide reconstruction + transform
+    Dw = wide_depth(cfg)
     data = g.field_get().astype(np.float64)
     o = oracle_of(g, cfg, keys, data)
     scale = np.abs(data).max()
     rng = np.random.default_rng(11)
-    picks = rng.choice(len(keys), size=min(150, len(keys)), replace=False)
+    picks = rng.choice(len(keys), size=min(60, len(keys)), replace=False)
     det = {}
+
+    def gpu_details(k):
+        if k not in det:
+            X = g.ghost_get(Dw, b0=index[k], nblk=1)[0].astype(np.float64)
+            det[k] = o.details_of(o.transform_of(X, Dw))
+        return det[k]
     er, ec = cfg["eps_refine"], cfg["eps_coarsen"]
-    mismatches = 0
+    in_band = 0
     for b in picks:
-        ref = o.block_norm(keys[b], det)
-        assert abs(nrm[b] - ref) <= 1e-5 * scale, (keys[b], nrm[b], ref)
-        L = keys[b][0]
+        k = keys[b]
+        L, i, j, kk = k
+        n = 1 << L
+        gpu_details(k)
+        for d in og.DIRS:
+            nk = (L, (i + d[0]) % n, (j + d[1]) % n, (kk + d[2]) % n)
+            if nk in index:
+                gpu_details(nk)
+        ref = o.block_norm(k, det)
+        assert abs(nrm[b] - ref) <= 1e-12 * ref + 1e-14 * scale, (k, nrm[b], ref)
         fg = (nrm[b] >= er and L < cfg["level_max"], nrm[b] <= ec and L > cfg["level_min"])
         fo = (ref >= er and L < cfg["level_max"], ref <= ec and L > cfg["level_min"])
-        if fg != fo:
-            band = min(abs(ref - er) - 1e-4 * er, abs(ref - ec) - 1e-4 * ec)
-            assert band <= 2e-7 * scale, (keys[b], nrm[b], ref)
-            mismatches += 1
-    assert mismatches <= len(picks) // 10
+        near = abs(ref - er) <= 1e-4 * er or abs(ref - ec) <= 1e-4 * ec
+        in_band += near
+        if not near:
+            assert fg == fo, (k, nrm[b], ref)
+    print("flags: %d sampled blocks, %d within the 1e-4 band" % (len(picks), in_band))
 
 
 def test_fullsize_fp32_step_vs_fp64(fullsize):
