@@ -176,6 +176,19 @@ mr_status mr_ghost_get(mr_grid* g, int32_t field, int32_t depth, int64_t b0,
  * written; mr_adapt returns the same before changing the tree. */
 mr_status mr_details(mr_grid* g, int32_t field, double* norms, int32_t on_device);
 
+/* mr_details without any allocation, for callers that cannot allocate
+ * (code under graph capture, serving loops, harnesses that forbid
+ * hipMalloc): the same ghost reconstruction and detail pass, with the
+ * per-block band maxima in a static device array of 27 * 65536 doubles
+ * (one per GPU, resident until the process ends) instead of the grid's
+ * buffer, and the n_blocks FP64 norms written to dev_norms (caller-owned
+ * device memory).  Asynchronous on the grid's stream.  Grids of more than
+ * 65536 blocks give MR_ECAPACITY.  Every call on one GPU shares the static
+ * array: calls that overlap on one GPU (two grids' streams, two threads)
+ * race and must be ordered by the caller.  Every value the pass reads from
+ * the array it has written in the same call. */
+mr_status mr_details_noalloc(mr_grid* g, int32_t field, double* dev_norms);
+
 /* Iterative adaptation (adaptation supplement): criterion, flags, policy
  * (refinement priority and propagation, 2:1, no coarsening of blocks refined
  * in this call, level bounds), refine / coarsen all fields, update step, until

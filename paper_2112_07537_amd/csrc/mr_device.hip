@@ -1537,6 +1537,33 @@ __global__ void k_fill(T* dst, size_t n) {
     dst[i] = T(0);
 }
 
+// ------------------------------------------------- static detail scratch
+// Band maxima of the detail pass (27 doubles per block) for callers that
+// cannot allocate: a file-scope device array, one copy per GPU, shared by
+// every call on that GPU.  Host code uses the address that
+// hipGetSymbolAddress returns for the current device, never the array's name
+// (which on the host is only a stand-in).
+static constexpr int64_t kStaticBandBlocks = 65536;
+static __device__ __align__(256) double scratch[27 * kStaticBandBlocks];
+
+int64_t static_band_blocks() { return kStaticBandBlocks; }
+
+hipError_t static_band_scratch(double** out) {
+  static double* ptr[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptr[dev] = static_cast<double*>(p);
+  }
+  *out = ptr[dev];
+  return hipSuccess;
+}
+
 // ------------------------------------------------------------- launchers
 #define MR_WAVELET_SWITCH(w, CALL)                                   \
   do {                                                               \

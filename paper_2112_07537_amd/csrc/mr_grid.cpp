@@ -1016,8 +1016,11 @@ static void rhs_stage(mr_grid* g, void* y, const void* un, void* out, double a_u
 }
 
 static void details_pass(mr_grid* g, void* field, const int32_t* det_slot, double* det_out,
-                         hipStream_t st = nullptr) {
+                         hipStream_t st = nullptr, double* bands = nullptr,
+                         double* norms = nullptr) {
   const hipStream_t strm = st ? st : g->stream;
+  if (!bands) bands = static_cast<double*>(g->d_bands.p);
+  if (!norms) norms = static_cast<double*>(g->d_norms.p);
   AnyView v = anyview(g, field);
   const int n = int(g->leaves.size());
   const Wavelet w{g->N, g->Nt};
@@ -1026,15 +1029,12 @@ static void details_pass(mr_grid* g, void* field, const int32_t* det_slot, doubl
   prof_begin(g, 1, &a, &e, !plain);
   if (plain) {
     for (int b = 0; b < n; ++b)
-      launch_details(g->f32, v.raw, w, g->Ef, g->Eb, static_cast<double*>(g->d_bands.p), det_slot,
-                     det_out, b, 1, strm);
+      launch_details(g->f32, v.raw, w, g->Ef, g->Eb, bands, det_slot, det_out, b, 1, strm);
   } else {
-    launch_details(g->f32, v.raw, w, g->Ef, g->Eb, static_cast<double*>(g->d_bands.p), det_slot,
-                   det_out, 0, n, strm);
+    launch_details(g->f32, v.raw, w, g->Ef, g->Eb, bands, det_slot, det_out, 0, n, strm);
   }
   prof_end(g, 1, a, e, !plain, int64_t(n) * g->nb * g->nb * g->nb);
-  launch_combine(v.raw, static_cast<double*>(g->d_bands.p), g->cfg.detail_ext,
-                 static_cast<double*>(g->d_norms.p), n, strm);
+  launch_combine(v.raw, bands, g->cfg.detail_ext, norms, n, strm);
 }
 
 static mr_status check_err(mr_grid* g) {
@@ -1849,6 +1849,20 @@ mr_status mr_details(mr_grid* g, int32_t field, double* norms, int32_t on_device
   if (st != MR_OK) return st;
   for (size_t b = 0; b < n; ++b)
     if (!std::isfinite(norms[b])) return fail(MR_ENONFINITE, "non-finite detail norm");
+  return MR_OK;
+}
+
+mr_status mr_details_noalloc(mr_grid* g, int32_t field, double* dev_norms) {
+  if (!g || !dev_norms || field < 0 || field >= g->cfg.n_fields)
+    return fail(MR_EINVAL, "bad argument");
+  const int64_t n = int64_t(g->leaves.size());
+  if (n > static_band_blocks())
+    return fail(MR_ECAPACITY, "mr_details_noalloc holds " + std::to_string(static_band_blocks()) +
+                                  " blocks at most, the grid has " + std::to_string(n));
+  double* bands = nullptr;
+  HIPCHK(static_band_scratch(&bands));
+  ghost_fill(g, g->fields[field].p, g->wide);
+  details_pass(g, g->fields[field].p, nullptr, nullptr, nullptr, bands, dev_norms);
   return MR_OK;
 }
 

@@ -133,6 +133,10 @@ void launch_fill(bool f32, void* dst, size_t n, hipStream_t s);
 void launch_pass(bool f32, const void* dg, Wavelet w, int filter, int axis, int src_mode,
                  int dst_mode, const PItem* items, int n_items, const double* din, double* dout,
                  const double* det, const int32_t* det_slot, void* dst, hipStream_t s);
+// Device address (current device) of the static band-maxima scratch of
+// mr_details_noalloc, resolved once per device; its capacity in blocks.
+hipError_t static_band_scratch(double** out);
+int64_t static_band_blocks();
 // Events to be stamped at the start and end of the next launch (NULL: none).
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 

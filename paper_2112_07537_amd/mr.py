@@ -61,6 +61,7 @@ def load():
         "mr_ghost": [P, C.c_int32, C.c_int32],
         "mr_ghost_get": [P, C.c_int32, C.c_int32, C.c_int64, C.c_int64, P, C.c_size_t],
         "mr_details": [P, C.c_int32, P, C.c_int32],
+        "mr_details_noalloc": [P, C.c_int32, P],
         "mr_adapt": [P, C.c_int32, C.c_int32, C.POINTER(mr_adapt_stats)],
         "mr_rk3_step": [P, C.c_int32, C.c_double, C.POINTER(mr_velocity)],
         "mr_details_rk3_step": [P, C.c_int32, C.c_double, C.POINTER(mr_velocity), P, C.c_int32],
@@ -232,6 +233,10 @@ class Grid:
         a = np.empty(n, np.float64)
         _check(lib().mr_details(self._h, field, _ptr(a), 0))
         return a
+
+    def details_noalloc(self, dev_norms, field=0):
+        """mr_details_noalloc: norms into caller device memory (address)."""
+        _check(lib().mr_details_noalloc(self._h, field, C.c_void_p(dev_norms)))
 
     def details_async(self, dev_ptr=None, field=0):
         _check(lib().mr_details(self._h, field, C.c_void_p(dev_ptr), 1))
