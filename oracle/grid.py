@@ -30,6 +30,8 @@ at a level-L grid point P, which is what the ghost reconstruction of section
     (READING: one restriction level).  For N.0 H^a is the identity, so this is
     plain injection.
 """
+from fractions import Fraction as Fr
+
 import numpy as np
 
 from . import wavelets as wv
@@ -48,6 +50,50 @@ def fd_weights(order):
         return {-3: -1.0 / 60, -2: 9.0 / 60, -1: -45.0 / 60,
                 1: 45.0 / 60, 2: -9.0 / 60, 3: 1.0 / 60}
     raise ValueError(order)
+
+
+# Stencils and ideal weights of the fixed-weight WENO fluxes (tables of the
+# finite-difference supplement, WENO order 3 and order 5): for f^+ at the
+# interface i+1/2 and for f^- at i-1/2, each candidate stencil S_r as
+# {offset from i: coefficient} with its ideal weight gamma_r.
+_WENO = {
+    3: dict(plus=[({-1: Fr(-1, 2), 0: Fr(3, 2)}, Fr(1, 3)),
+                  ({0: Fr(1, 2), 1: Fr(1, 2)}, Fr(2, 3))],
+            minus=[({-1: Fr(1, 2), 0: Fr(1, 2)}, Fr(2, 3)),
+                   ({0: Fr(3, 2), 1: Fr(-1, 2)}, Fr(1, 3))]),
+    5: dict(plus=[({-2: Fr(1, 3), -1: Fr(-7, 6), 0: Fr(11, 6)}, Fr(1, 10)),
+                  ({-1: Fr(-1, 6), 0: Fr(5, 6), 1: Fr(1, 3)}, Fr(3, 5)),
+                  ({0: Fr(1, 3), 1: Fr(5, 6), 2: Fr(-1, 6)}, Fr(3, 10))],
+            minus=[({-2: Fr(-1, 6), -1: Fr(5, 6), 0: Fr(1, 3)}, Fr(3, 10)),
+                   ({-1: Fr(1, 3), 0: Fr(5, 6), 1: Fr(-1, 6)}, Fr(3, 5)),
+                   ({0: Fr(11, 6), 1: Fr(-7, 6), 2: Fr(1, 3)}, Fr(1, 10))]),
+}
+
+
+def cons_fluxes(order, exact=False):
+    """CONS-3 / CONS-5 (finite-difference supplement): the fixed-weight WENO
+    interface fluxes, sum_r gamma_r S_r.  Returns (plus, minus) as
+    {offset: coefficient} for the flux at the interface i+1/2 built from the
+    values f_{i+offset}: plus is f^+_{i+1/2}, minus is f^-_{i+1/2} (the
+    tabulated f^-_{i-1/2} shifted by one point)."""
+    t = _WENO[order]
+    plus, minus = {}, {}
+    for st, gm in t["plus"]:
+        for o, c in st.items():
+            plus[o] = plus.get(o, 0) + gm * c
+    for st, gm in t["minus"]:
+        for o, c in st.items():
+            minus[o + 1] = minus.get(o + 1, 0) + gm * c
+    if not exact:
+        plus = {o: float(c) for o, c in plus.items()}
+        minus = {o: float(c) for o, c in minus.items()}
+    return plus, minus
+
+
+def stencil_depth(order):
+    """Ghost points a block's RHS reads: FD4 and CONS-3 two, FD6 and CONS-5
+    three."""
+    return {3: 2, 4: 2, 5: 3, 6: 3}[order]
 
 
 def transform_reach(N, Nt):
@@ -416,10 +462,14 @@ class Grid:
         raise ValueError(kind)
 
     def rhs_block(self, key, vel):
-        """-(u . grad) phi with central FD of order 4 or 6 on the ghost-filled
-        block.  Equal to -div(u phi) for the velocity fields used here, where
-        each u_d does not depend on x_d (conservative form, transport problem
-        of section 5 / finite-difference supplement)."""
+        """Right-hand side of the transport problem of section 5 on the
+        ghost-filled block.  fd_order 4 / 6: -(u . grad) phi with central FD
+        of that order, equal to -div(u phi) for the velocity fields used
+        here, where each u_d does not depend on x_d.  fd_order 3 / 5: the
+        conservative CONS-3 / CONS-5 form of the finite-difference
+        supplement (see cons_rhs_block)."""
+        if self.fd_order in (3, 5):
+            return self.cons_rhs_block(key, vel)
         g = self.fd_order // 2
         Xg = self.ghost_block(key, g)
         nb = self.nb
@@ -431,6 +481,45 @@ class Grid:
         dz = sum(w[o] * Xg[g + o:g + o + nb, core, core] for o in sorted(w)) / h
         ux, uy, uz = self.velocity(vel, *self.positions(key))
         return -(ux * dx + uy * dy + uz * dz)
+
+    def cons_rhs_block(self, key, vel):
+        """Conservative RHS of the finite-difference supplement:
+        d phi_i / dt = -sum_d (f_{i+1/2} - f_{i-1/2}) / h with f = u_d phi and
+        the fixed-weight WENO interface flux of order 3 or 5 (cons_fluxes):
+        f^+ where the interface velocity is positive, f^- where it is
+        negative.  READING (the interface velocity printed as the mean of
+        u_{i+1} and u_{i-1}): u_{i+1/2} = (u_i + u_{i+1}) / 2; for the
+        velocity fields used here u_d does not vary along x_d, so both
+        readings give u_d itself."""
+        g = stencil_depth(self.fd_order)
+        nb = self.nb
+        L = key[0]
+        h = 1.0 / (nb << L)
+        Xg = self.ghost_block(key, g)
+        o = self.origin(key)
+        den = float(nb << L)
+        ext = np.arange(-g, nb + g)
+        u = self.velocity(vel, (o[0] + ext) / den, (o[1] + ext) / den, (o[2] + ext) / den)
+        plus, minus = cons_fluxes(self.fd_order)
+        out = np.zeros((nb, nb, nb))
+        for a, ax in ((0, 2), (1, 1), (2, 0)):          # x, y, z; array axis
+            f = u[a] * Xg                                 # flux u_d phi
+            fa = np.moveaxis(f, ax, -1)
+            ua = np.moveaxis(u[a], ax, -1)
+            # interfaces i+1/2 for i = -1 .. nb-1 (window index g-1 .. g+nb-1)
+            fl = []
+            for i in range(g - 1, g + nb):
+                up = sum(c * fa[..., i + k] for k, c in sorted(plus.items()))
+                dn = sum(c * fa[..., i + k] for k, c in sorted(minus.items()))
+                ui = 0.5 * (ua[..., i] + ua[..., i + 1])
+                fl.append(np.where(ui > 0, up, dn))
+            F = np.stack(fl, axis=-1)                    # [..., nb + 1]
+            d = (F[..., 1:] - F[..., :-1]) / h
+            d = np.moveaxis(d, -1, ax)
+            sl = [slice(g, g + nb)] * 3
+            sl[ax] = slice(None)
+            out -= d[tuple(sl)]
+        return out
 
     def rk3_step(self, dt, vel):
         """SSP-RK3 of the time-integration supplement (standard Gottlieb-Shu
