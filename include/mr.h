@@ -66,7 +66,11 @@ typedef struct {
                           (else MR_EINVAL at creation)                      */
   int32_t wavelet_N;   /* interpolation order N: 2, 4 or 6                  */
   int32_t wavelet_Nt;  /* vanishing moments Nt: 0 (Donoho) or 2 (lifted)    */
-  int32_t fd_order;    /* central first-derivative order: 4 or 6            */
+  int32_t fd_order;    /* right-hand side: 4 or 6 = central finite
+                          differences of that order on -(u . grad) phi;
+                          3 or 5 = the conservative CONS-3 / CONS-5
+                          fixed-weight WENO fluxes of the finite-difference
+                          supplement (f^+ / f^- by the velocity's sign)     */
   int32_t level_min;   /* 0 <= level_min <= level_max <= 12                 */
   int32_t level_max;
   int32_t prec;        /* mr_prec of field arrays                           */
@@ -157,7 +161,8 @@ mr_status mr_init_ic(mr_grid* g, int32_t field, const mr_ic* ic, int32_t max_ite
  * block next to a coarser leaf, degree 1, 2 then 3 over the whole level
  * (section 2.3), written into the field; the patches of every coarse block
  * inside its finer regions (restriction of the substituted finer data).
- * Patches are `depth` points deep (0 = stencil depth fd_order/2).
+ * Patches are `depth` points deep (0 = the stencil depth: 2 for
+ * fd_order 3 and 4, 3 for 5 and 6).
  * Asynchronous. */
 mr_status mr_ghost(mr_grid* g, int32_t field, int32_t depth);
 
@@ -200,8 +205,9 @@ mr_status mr_details_noalloc(mr_grid* g, int32_t field, double* dev_norms);
  * library-owned buffer of the current tree's size for this.  Synchronises. */
 mr_status mr_adapt(mr_grid* g, int32_t field, int32_t max_iter, mr_adapt_stats* stats);
 
-/* One SSP-RK3 step of `field` (time-integration supplement) with central FD
- * advection; each stage reconstructs the ghosts first.  Asynchronous. */
+/* One SSP-RK3 step of `field` (time-integration supplement) with the
+ * configured right-hand side (central FD or CONS-3 / CONS-5); each stage
+ * reconstructs the ghosts first.  Asynchronous. */
 mr_status mr_rk3_step(mr_grid* g, int32_t field, double dt, const mr_velocity* vel);
 
 /* Fused step: the block criterion of `field` (as mr_details), then one

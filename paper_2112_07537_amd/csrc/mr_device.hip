@@ -889,14 +889,46 @@ __global__ __launch_bounds__(256) void k_restrict(DevGrid<T> g, const RItem* __r
 template <int FD> struct FDW;
 template <> struct FDW<4> {
   static constexpr int G = 2;
+  static constexpr bool CONS = false;
   // d/dx ~ (c1 (f[+1]-f[-1]) + c2 (f[+2]-f[-2])) / h
   __device__ static constexpr double c(int k) { return k == 1 ? 8.0 / 12.0 : -1.0 / 12.0; }
+  __device__ static constexpr double cp(int) { return 0.0; }
+  __device__ static constexpr double cm(int) { return 0.0; }
 };
 template <> struct FDW<6> {
   static constexpr int G = 3;
+  static constexpr bool CONS = false;
   __device__ static constexpr double c(int k) {
     return k == 1 ? 45.0 / 60.0 : (k == 2 ? -9.0 / 60.0 : 1.0 / 60.0);
   }
+  __device__ static constexpr double cp(int) { return 0.0; }
+  __device__ static constexpr double cm(int) { return 0.0; }
+};
+// CONS-3 / CONS-5 (finite-difference supplement): the flux difference
+// f_{i+1/2} - f_{i-1/2} of the fixed-weight WENO fluxes, sum_r gamma_r S_r of
+// the order-3 / order-5 stencil tables, written as one stencil on phi at the
+// offsets -G..G: cp for a positive velocity (f^+), cm for a negative one
+// (f^-).  With f^+_{i+1/2} = sum_o a_o f_{i+o}, the difference has the weight
+// a_o - a_{o+1} at offset o; order 3: a = (-1/6, 5/6, 1/3) at -1..1, order 5:
+// a = (2, -13, 47, 27, -3)/60 at -2..2; f^- mirrors them.
+template <> struct FDW<3> {
+  static constexpr int G = 2;
+  static constexpr bool CONS = true;
+  __device__ static constexpr double c(int) { return 0.0; }
+  __device__ static constexpr double cp(int o) {
+    return o == -2 ? 1.0 / 6.0 : o == -1 ? -1.0 : o == 0 ? 0.5 : o == 1 ? 1.0 / 3.0 : 0.0;
+  }
+  __device__ static constexpr double cm(int o) { return -cp(-o); }
+};
+template <> struct FDW<5> {
+  static constexpr int G = 3;
+  static constexpr bool CONS = true;
+  __device__ static constexpr double c(int) { return 0.0; }
+  __device__ static constexpr double cp(int o) {
+    return o == -3 ? -2.0 / 60.0 : o == -2 ? 15.0 / 60.0 : o == -1 ? -60.0 / 60.0
+         : o == 0 ? 20.0 / 60.0 : o == 1 ? 30.0 / 60.0 : o == 2 ? -3.0 / 60.0 : 0.0;
+  }
+  __device__ static constexpr double cm(int o) { return -cp(-o); }
 };
 
 template <typename T, int FD, int NB>
@@ -1026,12 +1058,35 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
     for (int k = 0; k < HPT; ++k) hv2[k] = (z + 2 < NB) ? load(hx[k], hy[k], z + 2) : T(0);
     __syncthreads();
     T dx = T(0), dy = T(0), dz = T(0);
+    T dxm = T(0), dym = T(0), dzm = T(0);
+    if constexpr (!FDW<FD>::CONS) {
 #pragma unroll
-    for (int kk = 1; kk <= G; ++kk) {
-      const T c = T(FDW<FD>::c(kk));
-      dx += c * (plane[(ty + G) * P + tx + G + kk] - plane[(ty + G) * P + tx + G - kk]);
-      dy += c * (plane[(ty + G + kk) * P + tx + G] - plane[(ty + G - kk) * P + tx + G]);
-      dz += c * (col[G + kk] - col[G - kk]);
+      for (int kk = 1; kk <= G; ++kk) {
+        const T c = T(FDW<FD>::c(kk));
+        dx += c * (plane[(ty + G) * P + tx + G + kk] - plane[(ty + G) * P + tx + G - kk]);
+        dy += c * (plane[(ty + G + kk) * P + tx + G] - plane[(ty + G - kk) * P + tx + G]);
+        dz += c * (col[G + kk] - col[G - kk]);
+      }
+    } else {
+      // both upwind differences; the sign of each velocity component picks
+      // one below
+#pragma unroll
+      for (int o = -G; o <= G; ++o) {
+        const T cp = T(FDW<FD>::cp(o)), cm = T(FDW<FD>::cm(o));
+        const T fx = plane[(ty + G) * P + tx + G + o];
+        const T fy = plane[(ty + G + o) * P + tx + G];
+        const T fz = col[G + o];
+        if (FDW<FD>::cp(o) != 0.0) {
+          dx += cp * fx;
+          dy += cp * fy;
+          dz += cp * fz;
+        }
+        if (FDW<FD>::cm(o) != 0.0) {
+          dxm += cm * fx;
+          dym += cm * fy;
+          dzm += cm * fz;
+        }
+      }
     }
     T ux, uy, uz;
     if (vel.kind == 2) {
@@ -1046,6 +1101,13 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
       ux = vx_z[0];
       uy = vy_x[0];
       uz = vz_y[0];
+    }
+    if constexpr (FDW<FD>::CONS) {
+      // u_d does not vary along x_d for these velocity fields, so the
+      // interface velocity u_{i+1/2} is u_d at the point
+      dx = ux > T(0) ? dx : dxm;
+      dy = uy > T(0) ? dy : dym;
+      dz = uz > T(0) ? dz : dzm;
     }
     const T rhs = -(ux * dx + uy * dy + uz * dz) * T(inv_h);
     const T yv = col[G];
@@ -1670,7 +1732,15 @@ template <typename T>
 static void rhs_t(const void* dgv, const void* un, void* out, int fd, double a, double b, double dt,
                   const VelDev& v, int first, int n, hipStream_t s) {
   const DevGrid<T>& g = *static_cast<const DevGrid<T>*>(dgv);
-  if (fd == 4) {
+  if (fd == 3) {
+    if (g.nb == 8) rhs_nb<T, 3, 8>(g, un, out, a, b, dt, v, first, n, s);
+    else if (g.nb == 16) rhs_nb<T, 3, 16>(g, un, out, a, b, dt, v, first, n, s);
+    else rhs_nb<T, 3, 24>(g, un, out, a, b, dt, v, first, n, s);
+  } else if (fd == 5) {
+    if (g.nb == 8) rhs_nb<T, 5, 8>(g, un, out, a, b, dt, v, first, n, s);
+    else if (g.nb == 16) rhs_nb<T, 5, 16>(g, un, out, a, b, dt, v, first, n, s);
+    else rhs_nb<T, 5, 24>(g, un, out, a, b, dt, v, first, n, s);
+  } else if (fd == 4) {
     if (g.nb == 8) rhs_nb<T, 4, 8>(g, un, out, a, b, dt, v, first, n, s);
     else if (g.nb == 16) rhs_nb<T, 4, 16>(g, un, out, a, b, dt, v, first, n, s);
     else rhs_nb<T, 4, 24>(g, un, out, a, b, dt, v, first, n, s);

@@ -1608,7 +1608,8 @@ mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, void* dev_pool,
   if (c.nb != 8 && c.nb != 16 && c.nb != 24) return fail(MR_EINVAL, "nb must be 8, 16 or 24");
   if (c.wavelet_N != 2 && c.wavelet_N != 4 && c.wavelet_N != 6) return fail(MR_EINVAL, "wavelet_N must be 2, 4 or 6");
   if (c.wavelet_Nt != 0 && c.wavelet_Nt != 2) return fail(MR_EINVAL, "wavelet_Nt must be 0 or 2");
-  if (c.fd_order != 4 && c.fd_order != 6) return fail(MR_EINVAL, "fd_order must be 4 or 6");
+  if (c.fd_order < 3 || c.fd_order > 6)
+    return fail(MR_EINVAL, "fd_order must be 4 or 6 (central) or 3 or 5 (CONS-3 / CONS-5)");
   if (c.level_min < 0 || c.level_max < c.level_min || c.level_max > 12)
     return fail(MR_EINVAL, "need 0 <= level_min <= level_max <= 12");
   if (c.prec != MR_F64 && c.prec != MR_F32) return fail(MR_EINVAL, "prec must be MR_F64 or MR_F32");
@@ -1651,7 +1652,7 @@ mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, void* dev_pool,
   g->nb = c.nb;
   g->N = c.wavelet_N;
   g->Nt = c.wavelet_Nt;
-  g->G = c.fd_order / 2;
+  g->G = (c.fd_order + 1) / 2;   // FD4 / CONS-3: 2, FD6 / CONS-5: 3
   const int H = Hreach(g->N, g->Nt);
   const int tf = std::max(H, g->N - 2), tb = std::max(H - 1, g->N - 1);
   g->Dw = std::max({g->G, tf, tb, g->N / 2, H});
