@@ -210,6 +210,21 @@ mr_status mr_adapt(mr_grid* g, int32_t field, int32_t max_iter, mr_adapt_stats* 
  * reconstructs the ghosts first.  Asynchronous. */
 mr_status mr_rk3_step(mr_grid* g, int32_t field, double dt, const mr_velocity* vel);
 
+/* One explicit stage (time-integration supplement; a building block for
+ * other explicit schemes and for a pure right-hand side): ghost
+ * reconstruction of field y (its substitution changes y in place), then
+ * out = a_un * un + b * (c_y * y + dt * L(y)) with L the configured
+ * right-hand side (-(u . grad) phi, or the CONS flux difference).  With
+ * a_un = 0, b = 1, c_y = 0, dt = 1, out = L(y).  y, un, out are field
+ * indices; out must differ from y (un may equal either).  Asynchronous. */
+mr_status mr_stage(mr_grid* g, int32_t y, int32_t un, int32_t out, double a_un, double b,
+                   double c_y, double dt, const mr_velocity* vel);
+
+/* Replace the refinement and coarsening thresholds of section 2.2.5 (used
+ * by the next mr_adapt / mr_details flag evaluation); needs
+ * eps_refine > eps_coarsen >= 0, else MR_EINVAL. */
+mr_status mr_set_thresholds(mr_grid* g, double eps_refine, double eps_coarsen);
+
 /* Fused step: the block criterion of `field` (as mr_details), then one
  * SSP-RK3 step of it (as mr_rk3_step), whose first stage uses the ghosts
  * that the criterion's wide reconstruction (section 2.2.5, Table 3) has

@@ -933,7 +933,7 @@ template <> struct FDW<5> {
 
 template <typename T, int FD, int NB>
 __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restrict__ un,
-                                                 T* __restrict__ out, T a_un, T b_y, T dt,
+                                                 T* __restrict__ out, T a_un, T b_y, T c_y, T dt,
                                                  VelDev vel, int first, int nxcd) {
   constexpr int G = FDW<FD>::G;
   constexpr int P = NB + 2 * G;
@@ -1111,7 +1111,9 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
     }
     const T rhs = -(ux * dx + uy * dy + uz * dz) * T(inv_h);
     const T yv = col[G];
-    __builtin_nontemporal_store(a_un * u0 + b_y * (yv + dt * rhs), &out[obase + (int64_t)z * NB * NB]);
+    const T res = c_y == T(1) ? a_un * u0 + b_y * (yv + dt * rhs)
+                              : a_un * u0 + b_y * (c_y * yv + dt * rhs);
+    __builtin_nontemporal_store(res, &out[obase + (int64_t)z * NB * NB]);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 2 * G; ++i) col[i] = col[i + 1];
@@ -1722,40 +1724,40 @@ void launch_rview(bool f32, const void* dg, Wavelet w, const RItem* items, int n
 }
 
 template <typename T, int FD, int NB>
-static void rhs_nb(const DevGrid<T>& g, const void* un, void* out, double a, double b, double dt,
-                   const VelDev& v, int first, int n, hipStream_t s) {
+static void rhs_nb(const DevGrid<T>& g, const void* un, void* out, double a, double b, double c,
+                   double dt, const VelDev& v, int first, int n, hipStream_t s) {
   const int nxcd = (n >= 64) ? 8 : 1;
   MR_LAUNCH((k_rhs<T, FD, NB>), dim3(n), dim3(NB * NB), 0, s, g, static_cast<const T*>(un),
-            static_cast<T*>(out), T(a), T(b), T(dt), v, first, nxcd);
+            static_cast<T*>(out), T(a), T(b), T(c), T(dt), v, first, nxcd);
 }
 template <typename T>
-static void rhs_t(const void* dgv, const void* un, void* out, int fd, double a, double b, double dt,
-                  const VelDev& v, int first, int n, hipStream_t s) {
+static void rhs_t(const void* dgv, const void* un, void* out, int fd, double a, double b, double c,
+                  double dt, const VelDev& v, int first, int n, hipStream_t s) {
   const DevGrid<T>& g = *static_cast<const DevGrid<T>*>(dgv);
   if (fd == 3) {
-    if (g.nb == 8) rhs_nb<T, 3, 8>(g, un, out, a, b, dt, v, first, n, s);
-    else if (g.nb == 16) rhs_nb<T, 3, 16>(g, un, out, a, b, dt, v, first, n, s);
-    else rhs_nb<T, 3, 24>(g, un, out, a, b, dt, v, first, n, s);
+    if (g.nb == 8) rhs_nb<T, 3, 8>(g, un, out, a, b, c, dt, v, first, n, s);
+    else if (g.nb == 16) rhs_nb<T, 3, 16>(g, un, out, a, b, c, dt, v, first, n, s);
+    else rhs_nb<T, 3, 24>(g, un, out, a, b, c, dt, v, first, n, s);
   } else if (fd == 5) {
-    if (g.nb == 8) rhs_nb<T, 5, 8>(g, un, out, a, b, dt, v, first, n, s);
-    else if (g.nb == 16) rhs_nb<T, 5, 16>(g, un, out, a, b, dt, v, first, n, s);
-    else rhs_nb<T, 5, 24>(g, un, out, a, b, dt, v, first, n, s);
+    if (g.nb == 8) rhs_nb<T, 5, 8>(g, un, out, a, b, c, dt, v, first, n, s);
+    else if (g.nb == 16) rhs_nb<T, 5, 16>(g, un, out, a, b, c, dt, v, first, n, s);
+    else rhs_nb<T, 5, 24>(g, un, out, a, b, c, dt, v, first, n, s);
   } else if (fd == 4) {
-    if (g.nb == 8) rhs_nb<T, 4, 8>(g, un, out, a, b, dt, v, first, n, s);
-    else if (g.nb == 16) rhs_nb<T, 4, 16>(g, un, out, a, b, dt, v, first, n, s);
-    else rhs_nb<T, 4, 24>(g, un, out, a, b, dt, v, first, n, s);
+    if (g.nb == 8) rhs_nb<T, 4, 8>(g, un, out, a, b, c, dt, v, first, n, s);
+    else if (g.nb == 16) rhs_nb<T, 4, 16>(g, un, out, a, b, c, dt, v, first, n, s);
+    else rhs_nb<T, 4, 24>(g, un, out, a, b, c, dt, v, first, n, s);
   } else {
-    if (g.nb == 8) rhs_nb<T, 6, 8>(g, un, out, a, b, dt, v, first, n, s);
-    else if (g.nb == 16) rhs_nb<T, 6, 16>(g, un, out, a, b, dt, v, first, n, s);
-    else rhs_nb<T, 6, 24>(g, un, out, a, b, dt, v, first, n, s);
+    if (g.nb == 8) rhs_nb<T, 6, 8>(g, un, out, a, b, c, dt, v, first, n, s);
+    else if (g.nb == 16) rhs_nb<T, 6, 16>(g, un, out, a, b, c, dt, v, first, n, s);
+    else rhs_nb<T, 6, 24>(g, un, out, a, b, c, dt, v, first, n, s);
   }
 }
 void launch_rhs(bool f32, const void* dg, const void* un, void* out, int fd, int depth, double a,
-                double b, double dt, const VelDev& v, int first, int n, hipStream_t s) {
+                double b, double c, double dt, const VelDev& v, int first, int n, hipStream_t s) {
   (void)depth;
   if (n <= 0) return;
-  if (f32) rhs_t<float>(dg, un, out, fd, a, b, dt, v, first, n, s);
-  else rhs_t<double>(dg, un, out, fd, a, b, dt, v, first, n, s);
+  if (f32) rhs_t<float>(dg, un, out, fd, a, b, c, dt, v, first, n, s);
+  else rhs_t<double>(dg, un, out, fd, a, b, c, dt, v, first, n, s);
 }
 
 template <typename T, int NB>

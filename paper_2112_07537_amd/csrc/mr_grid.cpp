@@ -1000,7 +1000,7 @@ static void ghost_fill(mr_grid* g, void* field, Lists& L, void* patch = nullptr)
 }
 
 static void rhs_stage(mr_grid* g, void* y, const void* un, void* out, double a_un, double b_y,
-                      double dt, const VelDev& vel, void* patch = nullptr) {
+                      double dt, const VelDev& vel, void* patch = nullptr, double c_y = 1.0) {
   AnyView v = anyview(g, y, patch);
   const int n = int(g->leaves.size());
   hipEvent_t a = nullptr, e = nullptr;
@@ -1008,9 +1008,11 @@ static void rhs_stage(mr_grid* g, void* y, const void* un, void* out, double a_u
   prof_begin(g, 0, &a, &e, !plain);
   if (plain) {
     for (int b = 0; b < n; ++b)
-      launch_rhs(g->f32, v.raw, un, out, g->cfg.fd_order, g->G, a_un, b_y, dt, vel, b, 1, g->stream);
+      launch_rhs(g->f32, v.raw, un, out, g->cfg.fd_order, g->G, a_un, b_y, c_y, dt, vel, b, 1,
+                 g->stream);
   } else {
-    launch_rhs(g->f32, v.raw, un, out, g->cfg.fd_order, g->G, a_un, b_y, dt, vel, 0, n, g->stream);
+    launch_rhs(g->f32, v.raw, un, out, g->cfg.fd_order, g->G, a_un, b_y, c_y, dt, vel, 0, n,
+               g->stream);
   }
   prof_end(g, 0, a, e, !plain, int64_t(n) * g->nb * g->nb * g->nb);
 }
@@ -1871,6 +1873,29 @@ mr_status mr_adapt(mr_grid* g, int32_t field, int32_t max_iter, mr_adapt_stats* 
   if (!g || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
   if (max_iter <= 0) max_iter = 64;
   return adapt_impl(g, field, max_iter, stats);
+}
+
+mr_status mr_stage(mr_grid* g, int32_t y, int32_t un, int32_t out, double a_un, double b,
+                   double c_y, double dt, const mr_velocity* vel) {
+  VelDev vd;
+  mr_status st = check_step_args(g, y, dt, vel, vd);
+  if (st != MR_OK) return st;
+  if (un < 0 || un >= g->cfg.n_fields || out < 0 || out >= g->cfg.n_fields || out == y)
+    return fail(MR_EINVAL, "stage fields: un, out in range and out != y");
+  if (!std::isfinite(a_un) || !std::isfinite(b) || !std::isfinite(c_y))
+    return fail(MR_EINVAL, "non-finite stage coefficient");
+  ghost_fill(g, g->fields[y].p, g->stage);
+  rhs_stage(g, g->fields[y].p, g->fields[un].p, g->fields[out].p, a_un, b, dt, vd, nullptr, c_y);
+  return MR_OK;
+}
+
+mr_status mr_set_thresholds(mr_grid* g, double eps_refine, double eps_coarsen) {
+  if (!g) return fail(MR_EINVAL, "null grid");
+  if (!(eps_refine > eps_coarsen) || !(eps_coarsen >= 0))
+    return fail(MR_EINVAL, "need eps_refine > eps_coarsen >= 0");
+  g->cfg.eps_refine = eps_refine;
+  g->cfg.eps_coarsen = eps_coarsen;
+  return MR_OK;
 }
 
 mr_status mr_rk3_step(mr_grid* g, int32_t field, double dt, const mr_velocity* vel) {

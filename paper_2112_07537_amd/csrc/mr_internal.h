@@ -108,9 +108,9 @@ void launch_subst(bool f32, const void* dg, Wavelet w, const GItem* items, int n
 void launch_cell_tables(bool f32, const void* dg, int n_blocks, hipStream_t s);
 void launch_rview(bool f32, const void* dg, Wavelet w, const RItem* items, int n_items,
                   int lds, int maxq, hipStream_t s);
-// RK3 stage: out = a*un + b*(y + dt*rhs(y)); stage 0 ignores un.
+// RK3 stage: out = a*un + b*(c*y + dt*rhs(y)) (c = 1 for the RK stages).
 void launch_rhs(bool f32, const void* dg_y, const void* un, void* out, int fd_order, int depth,
-                double a_un, double b_y, double dt, const VelDev& vel, int first_blk,
+                double a_un, double b_y, double c_y, double dt, const VelDev& vel, int first_blk,
                 int n_blk, hipStream_t s);
 // Details: per-block band maxima (27 per block, FP64), optional full detail
 // array of selected blocks (det_slot[b] >= 0) into det_out.

@@ -64,6 +64,9 @@ def load():
         "mr_details_noalloc": [P, C.c_int32, P],
         "mr_adapt": [P, C.c_int32, C.c_int32, C.POINTER(mr_adapt_stats)],
         "mr_rk3_step": [P, C.c_int32, C.c_double, C.POINTER(mr_velocity)],
+        "mr_stage": [P, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
+                     C.c_double, C.POINTER(mr_velocity)],
+        "mr_set_thresholds": [P, C.c_double, C.c_double],
         "mr_details_rk3_step": [P, C.c_int32, C.c_double, C.POINTER(mr_velocity), P, C.c_int32],
         "mr_cfl_dt": [P, C.POINTER(mr_velocity), C.c_double, C.POINTER(C.c_double)],
         "mr_block_meta": [P, C.c_int64, C.POINTER(C.c_int64), P, P],
@@ -233,6 +236,17 @@ class Grid:
         a = np.empty(n, np.float64)
         _check(lib().mr_details(self._h, field, _ptr(a), 0))
         return a
+
+    def stage(self, y, un, out, a_un, b, c_y, dt, vel):
+        """mr_stage: out = a_un*un + b*(c_y*y + dt*L(y)) after y's ghost fill."""
+        _check(lib().mr_stage(self._h, y, un, out, a_un, b, c_y, dt, C.byref(vel)))
+
+    def rhs(self, y, out, vel):
+        """L(y) into field `out` (mr_stage with a_un = 0, b = 1, c_y = 0, dt = 1)."""
+        self.stage(y, y, out, 0.0, 1.0, 0.0, 1.0, vel)
+
+    def set_thresholds(self, eps_refine, eps_coarsen):
+        _check(lib().mr_set_thresholds(self._h, eps_refine, eps_coarsen))
 
     def details_noalloc(self, dev_norms, field=0):
         """mr_details_noalloc: norms into caller device memory (address)."""
