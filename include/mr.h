@@ -205,6 +205,18 @@ mr_status mr_details_noalloc(mr_grid* g, int32_t field, double* dev_norms);
  * library-owned buffer of the current tree's size for this.  Synchronises. */
 mr_status mr_adapt(mr_grid* g, int32_t field, int32_t max_iter, mr_adapt_stats* stats);
 
+/* One adaptation iteration with block statuses given by the caller instead
+ * of the criterion (a prescribed adaptation, e.g. the static two-level grids
+ * of the convergence test of section 4.3): flags[b] for block b in the order
+ * of mr_block_meta is +1 (refine, below level_max), -1 (coarsen, above
+ * level_min) or 0 (keep).  The policy of the adaptation supplement applies:
+ * refinement propagates to coarser neighbours, and a sibling set coarsens
+ * only when all eight are flagged and no neighbour is finer or refining.
+ * Every field is refined / coarsened / updated as in mr_adapt.  flags is
+ * host memory of mr_grid_n_blocks entries; other values give MR_EINVAL.
+ * Transactional like mr_adapt.  Synchronises. */
+mr_status mr_adapt_flags(mr_grid* g, const int8_t* flags, mr_adapt_stats* stats);
+
 /* One SSP-RK3 step of `field` (time-integration supplement) with the
  * configured right-hand side (central FD or CONS-3 / CONS-5); each stage
  * reconstructs the ghosts first.  Asynchronous. */
@@ -261,8 +273,17 @@ mr_status mr_field_set(mr_grid* g, int32_t field, const void* host, size_t bytes
 mr_status mr_field_ptr(mr_grid* g, int32_t field, void** dev_ptr);
 
 /* FP64 discrete moments (section 2.1.4, per axis): out[0] = sum h^3 phi,
- * out[1..3] = sum h^3 phi x_d.  Synchronises. */
+ * out[1..3] = sum h^3 phi x_d, x_d the point coordinates in [0, 1).  Block
+ * partials are added on the host with a compensated sum, so the result is
+ * reproducible bit for bit.  Synchronises. */
 mr_status mr_moments(mr_grid* g, int32_t field, double out[4]);
+
+/* Distance of a field to an analytic initial condition evaluated in FP64 at
+ * the leaves' points (the error norms of the validation experiments of
+ * section 4: the epsilon test compares the compressed-and-refined field with
+ * the field sampled on the finest level): out[0] = max |phi - f|,
+ * out[1] = sqrt(sum h^3 (phi - f)^2).  Synchronises. */
+mr_status mr_ic_error(mr_grid* g, int32_t field, const mr_ic* ic, double out[2]);
 
 /* Kernel timing with HIP events recorded on the grid's stream around each
  * launch of the named kernel family ("rhs", "details", "ghost_refine",

@@ -179,7 +179,9 @@ class Grid:
                 s = l - L
                 bx, by, bz = (X << s) // self.nb, (Y << s) // self.nb, (Z << s) // self.nb
             code = bx + (by << 21) + (bz << 42)
-            lev[np.isin(code, self._keys[l])] = l
+            ks = self._keys[l]                     # sorted codes of level l
+            pos = np.minimum(np.searchsorted(ks, code), len(ks) - 1)
+            lev[ks[pos] == code] = l
         assert (lev >= 0).all(), "point outside every leaf"
         return lev
 
@@ -340,19 +342,17 @@ class Grid:
                 rng.append((0, N) if d[a] < 0 else (nb - N + 1, nb))
         return rng
 
-    def substitution_mask(self, key):
-        """Points of block ``key`` whose neglected details are discarded: the
-        union, over the directions with a coarser leaf, of the R-SUB slab
-        points taken by the selector (lifted: every point with an odd index;
-        unlifted: even on the facing axes and odd on a tangential axis)."""
+    def extension_mask(self, dirs):
+        """Points of a fine block whose details the coarse-extension assumption
+        discards toward coarser regions in the directions ``dirs``: the union of
+        the R-SUB slabs taken by the selector (lifted: every point with an odd
+        index; unlifted: even on the facing axes and odd on a tangential
+        axis)."""
         nb = self.nb
-        L = key[0]
         z, y, x = np.meshgrid(np.arange(nb), np.arange(nb), np.arange(nb), indexing="ij")
         pos = (x, y, z)
         M = np.zeros((nb, nb, nb), bool)
-        for d in DIRS:
-            if self.neighbor_level(key, d) >= L:
-                continue
+        for d in dirs:
             rng = self.substitution_slab(d)
             inr = np.ones((nb, nb, nb), bool)
             for a in range(3):
@@ -370,6 +370,12 @@ class Grid:
                 take &= tang_odd
             M |= inr & take
         return M
+
+    def substitution_mask(self, key):
+        """Points of block ``key`` whose neglected details are discarded: the
+        extension mask over the directions with a coarser leaf."""
+        L = key[0]
+        return self.extension_mask([d for d in DIRS if self.neighbor_level(key, d) < L])
 
     def substitution_values(self, key, deg, M):
         """Substitution of section 2.3 for the points of degree ``deg`` (number
@@ -751,11 +757,12 @@ class Grid:
             V = np.moveaxis(out, -1, ax_arr)
         return V
 
-    def _update_delta(self, fkey, coarsened_children):
+    def _update_delta(self, fkey, discarded):
         """Update step of section 2.2.1 / Table 3 for a kept block at level L
         next to a new coarse parent: the inverse transform (z, then y, then x)
-        of the discarded level-(L-1) details, with all scaling coefficients
-        zero, evaluated on the block's points."""
+        of the discarded level-(L-1) details (``discarded``: block key ->
+        detail array, zero where kept), with all scaling coefficients zero,
+        evaluated on the block's points."""
         t = wv.table(self.N, self.Nt)
         r = max(max(t["Js"]), max(t["Ks"]))
         L = fkey[0]
@@ -766,7 +773,7 @@ class Grid:
         W = self.width(L)
         Dd = np.zeros(X.shape)
         bx, by, bz = (X % W) // nb, (Y % W) // nb, (Z % W) // nb
-        for ck, det in coarsened_children.items():
+        for ck, det in discarded.items():
             if ck[0] != L:
                 continue
             m = (bx == ck[1]) & (by == ck[2]) & (bz == ck[3])
@@ -795,9 +802,16 @@ class Grid:
                         ck = (L, 2 * p[1] + cx, 2 * p[2] + cy, 2 * p[3] + cz)
                         children[ck] = None
         deltas = {}
-        # In 3D the update is needed for N.0 as well: the tensor inverse
-        # transform carries discarded details of one axis into the fine
-        # neighbour along another (3D values of the update column of Table 3).
+        # The discarded details are those of the coarsened children and, in
+        # each kept same-level neighbour, its coarse-extension slab toward the
+        # new parent: section 2.2.1 discards, with a coarsening neighbour, the
+        # fine side's details up to the coarse region extension distance of
+        # Table 3 as well (for 2.2 in 1D: gamma_2^0 when the region in front
+        # coarsens), and the update subtracts the synthesis of all of them
+        # (READING R-UPD).  In 3D the update is needed for N.0 as well: the
+        # tensor inverse transform carries discarded details of one axis into
+        # the fine neighbour along another (3D values of the update column of
+        # Table 3).
         if children:
             for ck in children:
                 children[ck] = self.block_details(ck)
@@ -806,8 +820,17 @@ class Grid:
                 for n in self.leaf_neighbors(ck):
                     if n[0] == ck[0] and n not in children and n not in refine:
                         kept_next.add(n)
+            discarded = dict(children)
             for fk in sorted(kept_next):
-                dlt = self._update_delta(fk, children)
+                L, i, j, k = fk
+                n = 1 << L
+                dirs = [d for d in DIRS if (L, (i + d[0]) % n, (j + d[1]) % n,
+                                             (k + d[2]) % n) in children]
+                M = self.extension_mask(dirs)
+                if M.any():
+                    discarded[fk] = np.where(M, self.block_details(fk), 0.0)
+            for fk in sorted(kept_next):
+                dlt = self._update_delta(fk, discarded)
                 if dlt is not None:
                     deltas[fk] = dlt
         blocks = {}

@@ -1408,10 +1408,39 @@ struct PassIO {
   double* dout;
   const double* det;
   const int32_t* det_slot;
+  const int32_t* det_dirs;  // per slot: kDiscardAll, or the directions of the
+                            // coarsening neighbours of a kept block
   T* dst;  // destination field array (new pool)
 };
 
-template <typename T>
+// Coarse-extension slab of a fine block toward the directions in `dirs`
+// (bit r = (dx+1) + 3 (dy+1) + 9 (dz+1)), whose details the update discards
+// with those of the coarsening neighbours (section 2.2.1, Table 3 coarse
+// region extension): along each facing axis [0, N) in front and
+// [nb-N+1, nb) behind, every point with an odd index (lifted); [0, N-1) and
+// [nb-N+2, nb), even on the facing axes and odd on a tangential one (N.0).
+template <int N, int NT>
+__device__ __forceinline__ bool in_extension(int nb, int x, int y, int z, int dirs) {
+  const int p[3] = {x, y, z};
+  const int front = NT ? N : N - 1;
+  const int back = NT ? nb - N + 1 : nb - N + 2;
+  for (int r = 0; r < 27; ++r) {
+    if (r == 13 || !((dirs >> r) & 1)) continue;
+    const int d[3] = {r % 3 - 1, (r / 3) % 3 - 1, r / 9 - 1};
+    bool in = true, face_even = true, tang_odd = false;
+    for (int a = 0; a < 3; ++a) {
+      if (d[a] < 0) in = in && p[a] < front;
+      else if (d[a] > 0) in = in && p[a] >= back;
+      if (d[a] != 0) face_even = face_even && (p[a] & 1) == 0;
+      else tang_odd = tang_odd || (p[a] & 1) != 0;
+    }
+    if (!in) continue;
+    if (NT ? ((x | y | z) & 1) != 0 : (face_even && tang_odd)) return true;
+  }
+  return false;
+}
+
+template <typename T, int N, int NT>
 __device__ __forceinline__ double pass_in(const DevGrid<T>& g, const PItem& it, int src_mode,
                                           const PassIO<T>& io, int x, int y, int z) {
   if (src_mode == 0) return double(ext_value(g, it.src_blk, x, y, z));
@@ -1424,7 +1453,8 @@ __device__ __forceinline__ double pass_in(const DevGrid<T>& g, const PItem& it, 
     }
     return io.din[it.in_off + ((int64_t)iz * it.isz[1] + iy) * it.isz[0] + ix];
   }
-  // src_mode 2: discarded details held by coarsening children (old tree)
+  // src_mode 2: discarded details (old tree): every detail of a coarsening
+  // child, the coarse-extension slab of a kept same-level neighbour
   const int id = owner_id(g, it.src_blk, 0, x, y, z);
   if (id < 0) return 0.0;
   const int s = io.det_slot[id];
@@ -1436,6 +1466,8 @@ __device__ __forceinline__ double pass_in(const DevGrid<T>& g, const PItem& it, 
   const int gx = wrapi(g.ijk[3 * it.src_blk] * nb + x, W) - g.ijk[3 * id] * nb;
   const int gy = wrapi(g.ijk[3 * it.src_blk + 1] * nb + y, W) - g.ijk[3 * id + 1] * nb;
   const int gz = wrapi(g.ijk[3 * it.src_blk + 2] * nb + z, W) - g.ijk[3 * id + 2] * nb;
+  const int dirs = io.det_dirs[s];
+  if (dirs != kDiscardAll && !in_extension<N, NT>(nb, gx, gy, gz, dirs)) return 0.0;
   return io.det[(int64_t)s * nb * nb * nb + ((int64_t)gz * nb + gy) * nb + gx];
 }
 
@@ -1457,7 +1489,7 @@ __global__ __launch_bounds__(256) void k_pass(DevGrid<T> g, const PItem* __restr
     double acc = 0.0;
     auto tap = [&](int c, double w) {
       q[axis] = c;
-      acc += w * pass_in(g, it, src_mode, io, q[0], q[1], q[2]);
+      acc += w * pass_in<T, N, NT>(g, it, src_mode, io, q[0], q[1], q[2]);
     };
     if (filter == F_REFINE) {
       if ((p & 1) == 0) {
@@ -1509,6 +1541,27 @@ __global__ __launch_bounds__(256) void k_pass(DevGrid<T> g, const PItem* __restr
 }
 
 // ------------------------------------------------------------- utilities
+__device__ __forceinline__ double ic_value(const IcDev& ic, double X, double Y, double Z) {
+  double v = 0.0;
+  if (ic.kind == 0) {
+    for (int k = 0; k < ic.n; ++k) {
+      const double* p = ic.params + 5 * k;
+      double dx = X - p[0], dy = Y - p[1], dz = Z - p[2];
+      dx -= round(dx);
+      dy -= round(dy);
+      dz -= round(dz);
+      v += p[4] * exp(-(dx * dx + dy * dy + dz * dz) / (p[3] * p[3]));
+    }
+  } else {
+    const double* p = ic.params;
+    const double ax = (X - 0.5) / p[0], ay = (Y - 0.5) / p[1], az = (Z - 0.5) / p[2];
+    const double rho = sqrt(ax * ax + ay * ay + az * az);
+    const double amin = fmin(p[0], fmin(p[1], p[2]));
+    v = 0.5 * (1.0 - tanh((rho - 1.0) * amin / p[3]));
+  }
+  return v;
+}
+
 template <typename T>
 __global__ void k_sample_ic(DevGrid<T> g, IcDev ic) {
   const int nb = g.nb;
@@ -1520,30 +1573,26 @@ __global__ void k_sample_ic(DevGrid<T> g, IcDev ic) {
     const int r = int(i % nb3);
     const int x = r % nb, y = (r / nb) % nb, z = r / (nb * nb);
     const double den = double(nb << g.lev[b]);
-    const double X = double(g.ijk[3 * b] * nb + x) / den;
-    const double Y = double(g.ijk[3 * b + 1] * nb + y) / den;
-    const double Z = double(g.ijk[3 * b + 2] * nb + z) / den;
-    double v = 0.0;
-    if (ic.kind == 0) {
-      for (int k = 0; k < ic.n; ++k) {
-        const double* p = ic.params + 5 * k;
-        double dx = X - p[0], dy = Y - p[1], dz = Z - p[2];
-        dx -= round(dx);
-        dy -= round(dy);
-        dz -= round(dz);
-        v += p[4] * exp(-(dx * dx + dy * dy + dz * dz) / (p[3] * p[3]));
-      }
-    } else {
-      const double* p = ic.params;
-      const double ax = (X - 0.5) / p[0], ay = (Y - 0.5) / p[1], az = (Z - 0.5) / p[2];
-      const double rho = sqrt(ax * ax + ay * ay + az * az);
-      const double amin = fmin(p[0], fmin(p[1], p[2]));
-      v = 0.5 * (1.0 - tanh((rho - 1.0) * amin / p[3]));
-    }
-    g.field[i] = T(v);
+    g.field[i] = T(ic_value(ic, double(g.ijk[3 * b] * nb + x) / den,
+                            double(g.ijk[3 * b + 1] * nb + y) / den,
+                            double(g.ijk[3 * b + 2] * nb + z) / den));
   }
 }
 
+// Block sums of 256 threads' FP64 partials (fixed order: deterministic).
+template <int K>
+__device__ __forceinline__ void block_sum(double (&s)[K], double (*red)[256]) {
+  for (int k = 0; k < K; ++k) red[k][threadIdx.x] = s[k];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int k = 0; k < K; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+    __syncthreads();
+  }
+}
+
+// Per-block moment partials out[4 b + k] (the host adds the blocks with a
+// compensated sum, so the result does not depend on the launch order).
 template <typename T>
 __global__ __launch_bounds__(256) void k_moments(DevGrid<T> g, double* out) {
   __shared__ double red[4][256];
@@ -1561,14 +1610,41 @@ __global__ __launch_bounds__(256) void k_moments(DevGrid<T> g, double* out) {
     s[2] += v * (double(g.ijk[3 * b + 1] * nb + y) / den);
     s[3] += v * (double(g.ijk[3 * b + 2] * nb + z) / den);
   }
-  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = s[k];
-  __syncthreads();
+  block_sum<4>(s, red);
+  if (threadIdx.x < 4) out[4 * (int64_t)b + threadIdx.x] = w * red[threadIdx.x][0];
+}
+
+// Per-block distance to the analytic field: out[2 b] = max |phi - f|,
+// out[2 b + 1] = sum h^3 (phi - f)^2, f evaluated in FP64 at the points.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ic_error(DevGrid<T> g, IcDev ic, double* out) {
+  __shared__ double red[1][256];
+  __shared__ double mx[256];
+  const int b = blockIdx.x;
+  const int nb = g.nb;
+  const int64_t nb3 = (int64_t)nb * nb * nb;
+  const double den = double(nb << g.lev[b]);
+  double s[1] = {0.0};
+  double m = 0.0;
+  for (int r = threadIdx.x; r < nb3; r += blockDim.x) {
+    const int x = r % nb, y = (r / nb) % nb, z = r / (nb * nb);
+    const double f = ic_value(ic, double(g.ijk[3 * b] * nb + x) / den,
+                              double(g.ijk[3 * b + 1] * nb + y) / den,
+                              double(g.ijk[3 * b + 2] * nb + z) / den);
+    const double e = double(g.field[b * nb3 + r]) - f;
+    s[0] += e * e;
+    m = fmax(m, fabs(e));
+  }
+  mx[threadIdx.x] = m;
+  block_sum<1>(s, red);
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st)
-      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+    if (threadIdx.x < st) mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + st]);
     __syncthreads();
   }
-  if (threadIdx.x < 4) atomicAdd(&out[threadIdx.x], w * red[threadIdx.x][0]);
+  if (threadIdx.x == 0) {
+    out[2 * (int64_t)b] = mx[0];
+    out[2 * (int64_t)b + 1] = red[0][0] / (den * den * den);
+  }
 }
 
 template <typename T>
@@ -1810,6 +1886,16 @@ void launch_moments(bool f32, const void* dgv, double* out, hipStream_t s) {
   }
 }
 
+void launch_ic_error(bool f32, const void* dgv, const IcDev& ic, double* out, hipStream_t s) {
+  if (f32) {
+    const DevGrid<float>& g = *static_cast<const DevGrid<float>*>(dgv);
+    if (g.nblk) hipLaunchKernelGGL(k_ic_error<float>, dim3(g.nblk), dim3(256), 0, s, g, ic, out);
+  } else {
+    const DevGrid<double>& g = *static_cast<const DevGrid<double>*>(dgv);
+    if (g.nblk) hipLaunchKernelGGL(k_ic_error<double>, dim3(g.nblk), dim3(256), 0, s, g, ic, out);
+  }
+}
+
 void launch_gather_ext(bool f32, const void* dgv, int depth, int64_t b0, int64_t nblk, void* out,
                        hipStream_t s) {
   if (nblk <= 0) return;
@@ -1845,18 +1931,21 @@ void launch_fill(bool f32, void* dst, size_t n, hipStream_t s) {
 template <typename T>
 static void pass_t(const void* dgv, Wavelet w, int filter, int axis, int src_mode, int dst_mode,
                    const PItem* items, int n, const double* din, double* dout, const double* det,
-                   const int32_t* slot, void* dst, hipStream_t s) {
+                   const int32_t* slot, const int32_t* dirs, void* dst, hipStream_t s) {
   const DevGrid<T>& g = *static_cast<const DevGrid<T>*>(dgv);
-  PassIO<T> io{din, dout, det, slot, static_cast<T*>(dst)};
+  PassIO<T> io{din, dout, det, slot, dirs, static_cast<T*>(dst)};
   MR_WAVELET_SWITCH(w, hipLaunchKernelGGL((k_pass<T, N_, NT_>), dim3(n), dim3(256), 0, s, g, items,
                                           filter, axis, src_mode, dst_mode, io));
 }
 void launch_pass(bool f32, const void* dgv, Wavelet w, int filter, int axis, int src_mode,
                  int dst_mode, const PItem* items, int n, const double* din, double* dout,
-                 const double* det, const int32_t* slot, void* dst, hipStream_t s) {
+                 const double* det, const int32_t* slot, const int32_t* dirs, void* dst,
+                 hipStream_t s) {
   if (n <= 0) return;
-  if (f32) pass_t<float>(dgv, w, filter, axis, src_mode, dst_mode, items, n, din, dout, det, slot, dst, s);
-  else pass_t<double>(dgv, w, filter, axis, src_mode, dst_mode, items, n, din, dout, det, slot, dst, s);
+  if (f32)
+    pass_t<float>(dgv, w, filter, axis, src_mode, dst_mode, items, n, din, dout, det, slot, dirs, dst, s);
+  else
+    pass_t<double>(dgv, w, filter, axis, src_mode, dst_mode, items, n, din, dout, det, slot, dirs, dst, s);
 }
 
 }  // namespace mr

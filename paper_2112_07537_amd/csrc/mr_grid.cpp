@@ -185,7 +185,7 @@ struct mr_grid {
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   HostTimer htime;
-  DevBuf ad_pairs, ad_items, ad_scr, ad_det, ad_slot;   // adaptation scratch
+  DevBuf ad_pairs, ad_items, ad_scr, ad_det, ad_slot, ad_dirs;   // adaptation scratch
   std::vector<DevBuf> backup;   // fields at the start of an mr_adapt call
   bool f32 = false;
   int nb = 16, N = 4, Nt = 0, G = 2, Dw = 4;
@@ -1060,6 +1060,10 @@ struct Plan {
   int refined = 0, coarsened = 0;
 };
 
+static void plan_from_flags(mr_grid* g, const std::vector<int>& flag,
+                            const std::unordered_set<uint64_t>& created, bool allow_coarsen,
+                            Plan& plan);
+
 // Flags (READING R-TIE: >= eps_r refines, <= eps_c may coarsen) and the
 // policy of the grid-adaptation supplement.
 static void make_plan(mr_grid* g, const std::vector<double>& norms,
@@ -1078,6 +1082,18 @@ static void make_plan(mr_grid* g, const std::vector<double>& norms,
     else if (v <= g->cfg.eps_coarsen && k.L > g->cfg.level_min) flag[b] = S_COARSER;
   }
   if (in_band) *in_band = band;
+  plan_from_flags(g, flag, created, allow_coarsen, plan);
+}
+
+// The adaptation policy of the grid-adaptation supplement on given block
+// statuses: refinement has priority and propagates to coarser neighbours
+// (2:1 after refining); a sibling set coarsens only if all eight leaves are
+// flagged, none was created by refinement in this adaptation, and no
+// neighbour is finer or refining.
+static void plan_from_flags(mr_grid* g, const std::vector<int>& flag,
+                            const std::unordered_set<uint64_t>& created, bool allow_coarsen,
+                            Plan& plan) {
+  const int n = int(g->leaves.size());
   plan.refine.assign(n, 0);
   std::vector<int> todo;
   for (int b = 0; b < n; ++b)
@@ -1211,6 +1227,23 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
         if (id >= 0 && slot[id] < 0) touches[id] = 1;
       }
     }
+    // discarded details per slot: all of a child's; of a kept neighbour,
+    // its coarse-extension slab toward the coarsening children (the update
+    // of section 2.2.1 discards those too, up to the coarse region
+    // extension of Table 3)
+    std::vector<int32_t> dirs(nslot, kDiscardAll);
+    for (int b = 0; b < n_old; ++b) {
+      if (!touches[b]) continue;
+      const Key& k = g->leaves[b];
+      int32_t m = 0;
+      for (int r = 0; r < 27; ++r) {
+        if (r == 13) continue;
+        const int id = find_leaf(g, k.L, k.i + r % 3 - 1, k.j + (r / 3) % 3 - 1, k.k + r / 9 - 1);
+        if (id >= 0 && slot[id] >= 0 && dirs[slot[id]] == kDiscardAll) m |= 1 << r;
+      }
+      slot[b] = nslot++;
+      dirs.push_back(m);
+    }
     const int H = Hreach(g->N, g->Nt);
     for (int b = 0; b < n_old; ++b) {
       const Key& k = g->leaves[b];
@@ -1312,6 +1345,10 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
     DevBuf& d_scr = g->ad_scr;
     DevBuf& d_det = g->ad_det;
     DevBuf& d_slot = g->ad_slot;
+    DevBuf& d_dirs = g->ad_dirs;
+    HIPCHK(d_dirs.ensure(std::max(1, nslot) * sizeof(int32_t)));
+    if (nslot)
+      HIPCHK(hipMemcpyAsync(d_dirs.p, dirs.data(), nslot * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
     HIPCHK(d_scr.ensure(std::max<int64_t>(1, scr) * sizeof(double)));
     HIPCHK(d_det.ensure(std::max<int64_t>(1, int64_t(nslot) * nb * nb * nb) * sizeof(double)));
     HIPCHK(d_slot.ensure(std::max(1, n_old) * sizeof(int32_t)));
@@ -1347,16 +1384,17 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
       // refine: x, y, z passes of the zero-detail refinement
       for (int p = 0; p < 3; ++p)
         launch_pass(g->f32, v.raw, w, F_REFINE, p, p == 0 ? 0 : 1, p == 2 ? 1 : 0, items + offs[p],
-                    int(ref[p].size()), scrp, scrp, nullptr, nullptr, dst, g->stream);
+                    int(ref[p].size()), scrp, scrp, nullptr, nullptr, nullptr, dst, g->stream);
       for (int p = 0; p < 3; ++p)
         launch_pass(g->f32, v.raw, w, F_RESTRICT, p, p == 0 ? 0 : 1, p == 2 ? 1 : 0, items + offs[3 + p],
-                    int(crs[p].size()), scrp, scrp, nullptr, nullptr, dst, g->stream);
+                    int(crs[p].size()), scrp, scrp, nullptr, nullptr, nullptr, dst, g->stream);
       // update: synthesis of the discarded details along z, then y, then x
       const int ax[3] = {2, 1, 0};
       for (int p = 0; p < 3; ++p)
         launch_pass(g->f32, v.raw, w, F_SYNTH, ax[p], p == 0 ? 2 : 1, p == 2 ? 2 : 0, items + offs[6 + p],
                     int(upd[p].size()), scrp, scrp, static_cast<const double*>(d_det.p),
-                    static_cast<const int32_t*>(d_slot.p), dst, g->stream);
+                    static_cast<const int32_t*>(d_slot.p), static_cast<const int32_t*>(d_dirs.p),
+                    dst, g->stream);
     }
     mr_status st = check_err(g);
     HIPCHK(hipStreamSynchronize(g->stream));
@@ -1380,7 +1418,37 @@ static mr_status norms_to_host(mr_grid* g, int field, std::vector<double>& out) 
   return MR_OK;
 }
 
-static mr_status adapt_iterations(mr_grid* g, int field, int max_iter, mr_adapt_stats* stats) {
+// One adaptation iteration with caller-given block statuses (no criterion).
+static mr_status adapt_with_flags(mr_grid* g, const int8_t* user, mr_adapt_stats* stats) {
+  const int n = int(g->leaves.size());
+  std::vector<int> flag(n, S_SAME);
+  for (int b = 0; b < n; ++b) {
+    const Key& k = g->leaves[b];
+    if (user[b] > 0 && k.L < g->cfg.level_max) flag[b] = S_FINER;
+    else if (user[b] < 0 && k.L > g->cfg.level_min) flag[b] = S_COARSER;
+  }
+  Plan plan;
+  plan_from_flags(g, flag, {}, true, plan);
+  mr_adapt_stats s{};
+  if (plan.refined || plan.coarsened) {
+    int64_t nn = int64_t(n) + 7 * int64_t(plan.refined) - 7 * int64_t(plan.coarsened);
+    if (nn > g->cfg.max_blocks)
+      return fail(MR_ECAPACITY, "adaptation needs " + std::to_string(nn) + " blocks, capacity " +
+                                    std::to_string(g->cfg.max_blocks));
+    mr_status st = apply_plan(g, plan, nullptr, false);
+    if (st != MR_OK) return st;
+    s.iters = 1;
+    s.refined = plan.refined;
+    s.coarsened = plan.coarsened;
+  }
+  s.n_blocks = int64_t(g->leaves.size());
+  if (stats) *stats = s;
+  return MR_OK;
+}
+
+static mr_status adapt_iterations(mr_grid* g, int field, int max_iter, mr_adapt_stats* stats,
+                                  const int8_t* user_flags = nullptr) {
+  if (user_flags) return adapt_with_flags(g, user_flags, stats);
   std::unordered_set<uint64_t> created;
   mr_adapt_stats s{};
   HostTimer& ht = g->htime;
@@ -1422,7 +1490,8 @@ static mr_status adapt_iterations(mr_grid* g, int field, int max_iter, mr_adapt_
 // (which the ghost reconstructions of the criterion substitute in place) are
 // saved first; when the call fails with MR_ECAPACITY or MR_ENONFINITE they
 // are restored bit for bit.
-static mr_status adapt_impl(mr_grid* g, int field, int max_iter, mr_adapt_stats* stats) {
+static mr_status adapt_impl(mr_grid* g, int field, int max_iter, mr_adapt_stats* stats,
+                            const int8_t* user_flags = nullptr) {
   const std::vector<Key> saved = g->leaves;
   const size_t bytes = g->leaves.size() * size_t(g->nb) * g->nb * g->nb * g->esz;
   g->backup.resize(g->cfg.n_fields);
@@ -1430,7 +1499,7 @@ static mr_status adapt_impl(mr_grid* g, int field, int max_iter, mr_adapt_stats*
     HIPCHK(g->backup[f].ensure(bytes));
     HIPCHK(hipMemcpyAsync(g->backup[f].p, g->fields[f].p, bytes, hipMemcpyDeviceToDevice, g->stream));
   }
-  mr_status st = adapt_iterations(g, field, max_iter, stats);
+  mr_status st = adapt_iterations(g, field, max_iter, stats, user_flags);
   if (st != MR_ECAPACITY && st != MR_ENONFINITE) return st;
   const std::string msg = g_errmsg;
   (void)hipStreamSynchronize(g->stream);
@@ -1568,7 +1637,7 @@ static void free_grid(mr_grid* g) {
                     &g->d_err, &g->d_bands, &g->d_norms, &g->d_icpar, &g->d_mom,
                     &g->stage.dg, &g->stage.ds, &g->stage.dr, &g->wide.dg, &g->wide.ds,
                     &g->wide.dr, &g->ad_pairs, &g->d_cbase, &g->d_cstep, &g->d_stab, &g->d_patch2,
-                    &g->ad_items, &g->ad_scr, &g->ad_det, &g->ad_slot};
+                    &g->ad_items, &g->ad_scr, &g->ad_det, &g->ad_slot, &g->ad_dirs};
   for (DevBuf* b : bufs) b->release();
   if (g->aux) {
     (void)hipEventDestroy(g->ev_fork);
@@ -1875,6 +1944,13 @@ mr_status mr_adapt(mr_grid* g, int32_t field, int32_t max_iter, mr_adapt_stats* 
   return adapt_impl(g, field, max_iter, stats);
 }
 
+mr_status mr_adapt_flags(mr_grid* g, const int8_t* flags, mr_adapt_stats* stats) {
+  if (!g || !flags) return fail(MR_EINVAL, "bad argument");
+  for (size_t b = 0; b < g->leaves.size(); ++b)
+    if (flags[b] < -1 || flags[b] > 1) return fail(MR_EINVAL, "block status must be -1, 0 or 1");
+  return adapt_impl(g, 0, 1, stats, flags);
+}
+
 mr_status mr_stage(mr_grid* g, int32_t y, int32_t un, int32_t out, double a_un, double b,
                    double c_y, double dt, const mr_velocity* vel) {
   VelDev vd;
@@ -1979,14 +2055,57 @@ mr_status mr_field_ptr(mr_grid* g, int32_t field, void** dev_ptr) {
   return MR_OK;
 }
 
+// Neumaier's compensated sum of the per-block partials (column c of rows of
+// width w): the result does not depend on the order the blocks ran in.
+static double compensated_sum(const std::vector<double>& a, int w, int c) {
+  double s = 0.0, comp = 0.0;
+  for (size_t i = c; i < a.size(); i += w) {
+    const double t = s + a[i];
+    comp += std::fabs(s) >= std::fabs(a[i]) ? (s - t) + a[i] : (a[i] - t) + s;
+    s = t;
+  }
+  return s + comp;
+}
+
 mr_status mr_moments(mr_grid* g, int32_t field, double out[4]) {
   if (!g || !out || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
-  const double z[4] = {0, 0, 0, 0};
-  HIPCHK(hipMemcpyAsync(g->d_mom.p, z, sizeof(z), hipMemcpyHostToDevice, g->stream));
+  const int n = int(g->leaves.size());
+  for (int k = 0; k < 4; ++k) out[k] = 0.0;
+  if (n == 0) return MR_OK;
+  HIPCHK(g->d_mom.ensure(4 * size_t(n) * sizeof(double)));
   AnyView v = anyview(g, g->fields[field].p);
   launch_moments(g->f32, v.raw, static_cast<double*>(g->d_mom.p), g->stream);
-  HIPCHK(hipMemcpyAsync(out, g->d_mom.p, 4 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+  std::vector<double> part(4 * size_t(n));
+  HIPCHK(hipMemcpyAsync(part.data(), g->d_mom.p, part.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, g->stream));
   HIPCHK(hipStreamSynchronize(g->stream));
+  for (int k = 0; k < 4; ++k) out[k] = compensated_sum(part, 4, k);
+  return MR_OK;
+}
+
+mr_status mr_ic_error(mr_grid* g, int32_t field, const mr_ic* ic, double out[2]) {
+  if (!g || !ic || !out || field < 0 || field >= g->cfg.n_fields)
+    return fail(MR_EINVAL, "bad argument");
+  if (ic->kind != MR_IC_GAUSS_SUM && ic->kind != MR_IC_TANH_SHELL)
+    return fail(MR_EINVAL, "unknown initial condition kind");
+  const int np = ic->kind == MR_IC_GAUSS_SUM ? 5 * ic->n : 4;
+  if (np <= 0 || !ic->params) return fail(MR_EINVAL, "initial condition without parameters");
+  out[0] = out[1] = 0.0;
+  const int n = int(g->leaves.size());
+  if (n == 0) return MR_OK;
+  HIPCHK(g->d_icpar.ensure(np * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(g->d_icpar.p, ic->params, np * sizeof(double), hipMemcpyHostToDevice,
+                        g->stream));
+  HIPCHK(g->d_mom.ensure(4 * size_t(n) * sizeof(double)));
+  IcDev d{ic->kind, ic->n, static_cast<const double*>(g->d_icpar.p)};
+  AnyView v = anyview(g, g->fields[field].p);
+  launch_ic_error(g->f32, v.raw, d, static_cast<double*>(g->d_mom.p), g->stream);
+  std::vector<double> part(2 * size_t(n));
+  HIPCHK(hipMemcpyAsync(part.data(), g->d_mom.p, part.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  for (int b = 0; b < n; ++b) out[0] = std::max(out[0], part[2 * size_t(b)]);
+  out[1] = std::sqrt(compensated_sum(part, 2, 1));
   return MR_OK;
 }
 

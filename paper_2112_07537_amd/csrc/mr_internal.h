@@ -120,7 +120,8 @@ void launch_details(bool f32, const void* dg, Wavelet w, int ef, int eb, double*
 void launch_combine(const void* dg_any, const double* bands, int detail_ext, double* norms,
                     int n_blk, hipStream_t s);
 void launch_sample_ic(bool f32, const void* dg, const IcDev& ic, hipStream_t s);
-void launch_moments(bool f32, const void* dg, double* out4, hipStream_t s);
+void launch_ic_error(bool f32, const void* dg, const IcDev& ic, double* out, hipStream_t s);
+void launch_moments(bool f32, const void* dg, double* out, hipStream_t s);  // 4 per block
 void launch_gather_ext(bool f32, const void* dg, int depth, int64_t b0, int64_t nblk, void* out,
                        hipStream_t s);
 void launch_copy_blocks(bool f32, const void* src, void* dst, const int32_t* pairs, int n_pairs,
@@ -132,7 +133,11 @@ void launch_fill(bool f32, void* dst, size_t n, hipStream_t s);
 // (block-local coordinates = output - dlo).
 void launch_pass(bool f32, const void* dg, Wavelet w, int filter, int axis, int src_mode,
                  int dst_mode, const PItem* items, int n_items, const double* din, double* dout,
-                 const double* det, const int32_t* det_slot, void* dst, hipStream_t s);
+                 const double* det, const int32_t* det_slot, const int32_t* det_dirs, void* dst,
+                 hipStream_t s);
+
+// det_dirs value of a coarsening child: all its details are discarded.
+constexpr int32_t kDiscardAll = 1 << 27;
 // Device address (current device) of the static band-maxima scratch of
 // mr_details_noalloc, resolved once per device; its capacity in blocks.
 hipError_t static_band_scratch(double** out);

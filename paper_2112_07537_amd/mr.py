@@ -67,6 +67,8 @@ def load():
         "mr_stage": [P, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
                      C.c_double, C.POINTER(mr_velocity)],
         "mr_set_thresholds": [P, C.c_double, C.c_double],
+        "mr_ic_error": [P, C.c_int32, C.POINTER(mr_ic), P],
+        "mr_adapt_flags": [P, P, C.POINTER(mr_adapt_stats)],
         "mr_details_rk3_step": [P, C.c_int32, C.c_double, C.POINTER(mr_velocity), P, C.c_int32],
         "mr_cfl_dt": [P, C.POINTER(mr_velocity), C.c_double, C.POINTER(C.c_double)],
         "mr_block_meta": [P, C.c_int64, C.POINTER(C.c_int64), P, P],
@@ -260,6 +262,15 @@ class Grid:
         _check(lib().mr_adapt(self._h, field, max_iter, C.byref(st)))
         return st
 
+    def adapt_flags(self, flags):
+        """mr_adapt_flags: one adaptation with caller block statuses (+1/0/-1)."""
+        f = np.ascontiguousarray(flags, dtype=np.int8)
+        if f.shape != (self.n_blocks(),):
+            raise ValueError("one status per block")
+        st = mr_adapt_stats()
+        _check(lib().mr_adapt_flags(self._h, f.ctypes.data_as(C.c_void_p), C.byref(st)))
+        return st
+
     def rk3_step(self, dt, vel, field=0):
         _check(lib().mr_rk3_step(self._h, field, dt, C.byref(vel)))
 
@@ -283,6 +294,13 @@ class Grid:
         a = np.zeros(4, np.float64)
         _check(lib().mr_moments(self._h, field, _ptr(a)))
         return a
+
+    def ic_error(self, kind, params, field=0):
+        """mr_ic_error: (max |phi - f|, L2 norm of phi - f) over the leaves."""
+        ic, par = self._ic(kind, params)
+        a = np.zeros(2, np.float64)
+        _check(lib().mr_ic_error(self._h, field, C.byref(ic), _ptr(a)))
+        return float(a[0]), float(a[1])
 
     def prof_enable(self, on=True):
         _check(lib().mr_prof_enable(self._h, int(on)))

@@ -176,6 +176,63 @@ def test_fullsize_fp32_step_vs_fp64(fullsize):
     assert np.abs(a - b).max() <= 1e-5 * scale
 
 
+def test_fullsize_stage_sampled(fullsize):
+    """One explicit stage at the benchmark size against the oracle, element
+    by element on 60 sampled blocks.  mr_stage reconstructs the ghosts of y
+    (substituting its slab points in place) and writes out = a*un +
+    b*(c*y + dt*L(y)); the oracle evaluates the same combination with its
+    own level view and right-hand side on the GPU's substituted y, with the
+    coarser regions refined from the samples before the substitution, and
+    its own substitution of 20 of the blocks checks y itself.  Tolerance:
+    1e-5 (FP32) / 1e-12 (FP64) of max|phi| for fields; a pure right-hand
+    side L(y) is compared after scaling by the block's spacing h (dt*L at
+    CFL one)."""
+    cfg, g = fullsize
+    keys = [tuple(int(v) for v in m) for m in g.block_meta()]
+    data = g.field_get()
+    rng = np.random.default_rng(13)
+    perm = rng.permutation(len(keys))
+    h = mr.Grid(cfg["nb"], cfg["N"], cfg["Nt"], fd_order=cfg["fd"], level_min=cfg["level_min"],
+                level_max=cfg["level_max"], prec=cfg["prec"], eps_refine=cfg["eps_refine"],
+                eps_coarsen=cfg["eps_coarsen"], n_fields=2, max_blocks=150000)
+    h.set_tree(keys)
+    kind, p = wl.velocity_spec(cfg["vel"])
+    v = mr.velocity(kind, *p)
+    dt = h.cfl_dt(v, cfg["cfl"])
+    d64 = data.astype(np.float64)
+    scale = np.abs(d64).max()
+    tol = (1e-5 if cfg["prec"] == "f32" else 1e-12) * scale
+    lv = np.array([k[0] for k in keys])
+    picks = list(rng.choice(len(keys), size=min(50, len(keys)), replace=False))
+    for L in (int(lv.min()), int(lv.max())):
+        cand = np.nonzero(lv == L)[0]
+        picks += list(rng.choice(cand, size=min(5, len(cand)), replace=False))
+    coef = [(0.75, 0.25, 1.0, dt), (0.0, 1.0, 0.0, 1.0)]
+    for a_un, b, c_y, dts in coef:
+        h.field_set(data, 0)
+        h.field_set(0.5 * data[perm], 1)
+        un = h.field_get(1).astype(np.float64)
+        h.stage(0, 1, 1, a_un, b, c_y, dts, v)
+        y = h.field_get(0).astype(np.float64)
+        out = h.field_get(1).astype(np.float64)
+        o = oracle_of(h, cfg, keys, y)
+        o._pre = {k: d64[b_] for b_, k in enumerate(keys)}
+        vel = (kind, tuple(p))
+        for b_ in picks:
+            k = keys[b_]
+            ref = a_un * un[b_] + b * (c_y * y[b_] + dts * o.rhs_block(k, vel))
+            hs = 1.0 / (cfg["nb"] << k[0]) if c_y == 0.0 else 1.0
+            err = np.abs(out[b_] - ref).max() * hs
+            assert err <= tol, (k, err, tol)
+    # the substitution of y itself, from the pre-stage data
+    o = oracle_of(h, cfg, keys, d64.copy())
+    sub = picks[:20]
+    o.substitute(keys=[keys[b_] for b_ in sub])
+    for b_ in sub:
+        np.testing.assert_allclose(y[b_], o.blocks[keys[b_]], rtol=0, atol=tol)
+    h.close()
+
+
 def test_fullsize_fused_matches_separate_calls(fullsize):
     """mr_details_rk3_step against mr_details + mr_rk3_step from the same
     state, at the benchmark size: the norms agree, and the fields after the
