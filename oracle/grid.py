@@ -327,8 +327,9 @@ class Grid:
         refinement takes as zero: lifted, the details around every even
         sample of the fine block that the refinement of its ghost points reads
         (N-1 points in front, N-2 behind) enter those samples through the
-        lifting; unlifted, only the tangential details at those samples enter
-        (the 3D inverse transform reads them along the facing axis).  Seen
+        lifting; unlifted, the tangential details at those samples enter (the
+        3D inverse transform reads them along the facing axis), and every
+        detail up to that distance is discarded (see extension_mask).  Seen
         from the neighbour that would coarsen, the far end of the slab lies at
         the distance of the 3D "coarse region extension" column of Table 3."""
         N, nb = self.N, self.nb
@@ -344,10 +345,14 @@ class Grid:
 
     def extension_mask(self, dirs):
         """Points of a fine block whose details the coarse-extension assumption
-        discards toward coarser regions in the directions ``dirs``: the union of
-        the R-SUB slabs taken by the selector (lifted: every point with an odd
-        index; unlifted: even on the facing axes and odd on a tangential
-        axis)."""
+        discards toward coarser regions in the directions ``dirs``: every
+        detail (point with an odd index, of any degree) in the union of the
+        R-SUB slabs.  In 3D the paper discards any first, second and third
+        degree detail involved in the multi-dimensional refinement, up to the
+        3D coarse region extension of Table 3 (section 2.3); for N.0 this is
+        wider than the 1D column (0), which applies to 1D grids (READING
+        R-SUB: with it the epsilon and moment tests of sections 4.1 and 4.2
+        reproduce the paper's printed values for 4.0 and 6.0)."""
         nb = self.nb
         z, y, x = np.meshgrid(np.arange(nb), np.arange(nb), np.arange(nb), indexing="ij")
         pos = (x, y, z)
@@ -357,19 +362,8 @@ class Grid:
             inr = np.ones((nb, nb, nb), bool)
             for a in range(3):
                 inr &= (pos[a] >= rng[a][0]) & (pos[a] < rng[a][1])
-            if self.Nt > 0:
-                take = (x % 2 + y % 2 + z % 2) > 0
-            else:
-                take = np.ones((nb, nb, nb), bool)
-                tang_odd = np.zeros((nb, nb, nb), bool)
-                for a in range(3):
-                    if d[a] != 0:
-                        take &= pos[a] % 2 == 0
-                    else:
-                        tang_odd |= pos[a] % 2 == 1
-                take &= tang_odd
-            M |= inr & take
-        return M
+            M |= inr
+        return M & ((x % 2 + y % 2 + z % 2) > 0)
 
     def substitution_mask(self, key):
         """Points of block ``key`` whose neglected details are discarded: the

@@ -1416,26 +1416,24 @@ struct PassIO {
 // Coarse-extension slab of a fine block toward the directions in `dirs`
 // (bit r = (dx+1) + 3 (dy+1) + 9 (dz+1)), whose details the update discards
 // with those of the coarsening neighbours (section 2.2.1, Table 3 coarse
-// region extension): along each facing axis [0, N) in front and
-// [nb-N+1, nb) behind, every point with an odd index (lifted); [0, N-1) and
-// [nb-N+2, nb), even on the facing axes and odd on a tangential one (N.0).
+// region extension): every point with an odd index within [0, N) in front
+// and [nb-N+1, nb) behind along each facing axis (lifted), [0, N-1) and
+// [nb-N+2, nb) (N.0).
 template <int N, int NT>
 __device__ __forceinline__ bool in_extension(int nb, int x, int y, int z, int dirs) {
+  if (((x | y | z) & 1) == 0) return false;
   const int p[3] = {x, y, z};
   const int front = NT ? N : N - 1;
   const int back = NT ? nb - N + 1 : nb - N + 2;
   for (int r = 0; r < 27; ++r) {
     if (r == 13 || !((dirs >> r) & 1)) continue;
     const int d[3] = {r % 3 - 1, (r / 3) % 3 - 1, r / 9 - 1};
-    bool in = true, face_even = true, tang_odd = false;
+    bool in = true;
     for (int a = 0; a < 3; ++a) {
       if (d[a] < 0) in = in && p[a] < front;
       else if (d[a] > 0) in = in && p[a] >= back;
-      if (d[a] != 0) face_even = face_even && (p[a] & 1) == 0;
-      else tang_odd = tang_odd || (p[a] & 1) != 0;
     }
-    if (!in) continue;
-    if (NT ? ((x | y | z) & 1) != 0 : (face_even && tang_odd)) return true;
+    if (in) return true;
   }
   return false;
 }

@@ -549,11 +549,10 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
             else { sb.lo[a] = nb - N + 1; sb.hi[a] = nb; }
           } else {
             if (d < 0) { sb.lo[a] = 0; sb.hi[a] = N - 1; }
-            else { sb.lo[a] = nb - N + 2; sb.hi[a] = nb - 1; }
+            else { sb.lo[a] = nb - N + 2; sb.hi[a] = nb; }
           }
           if (sb.hi[a] <= sb.lo[a]) sempty = true;
         }
-        if (!Nt && facing == 7) sempty = true;  // corner: no tangential axis
         bool covered = false;
         for (int sub = 1; sub < 8 && !covered; ++sub) {
           if ((sub & facing) != sub || sub == facing) continue;
@@ -693,8 +692,8 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
     }
   }
   {
-    // slab points (the kernel's selector) and staged lattice points per item
-    const int FL = Nt ? N : N - 1, BL = Nt ? nb - N + 1 : nb - N + 2;
+    // slab points (every point of the item boxes but the all-even ones) and
+    // staged lattice points per item
     for (const GItem& it : L.s) {
       int64_t vol = 1, ev = 1, lat = 1;
       for (int a = 0; a < 3; ++a) {
@@ -706,19 +705,7 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
         lat *= c;
       }
       L.sb_r += lat;
-      if (Nt) {
-        L.sb_w += vol - ev;   // lifted: every point of the slabs but the all-even ones
-        continue;
-      }
-      const uint64_t* t = &g->stab_host[size_t(it.blk) * 8];
-      for (int z = it.lo[2]; z < it.hi[2]; ++z)
-        for (int y = it.lo[1]; y < it.hi[1]; ++y)
-          for (int x = it.lo[0]; x < it.hi[0]; ++x) {
-            const int idx = (x < FL) | ((y < FL) << 1) | ((z < FL) << 2) | ((x >= BL) << 3) |
-                            ((y >= BL) << 4) | ((z >= BL) << 5) |
-                            (((x & 1) | ((y & 1) << 1) | ((z & 1) << 2)) << 6);
-            L.sb_w += (t[idx >> 6] >> (idx & 63)) & 1;
-          }
+      L.sb_w += vol - ev;
     }
   }
   for (const RItem& it : L.r) {
@@ -838,14 +825,12 @@ static mr_status commit_tree_impl(mr_grid* g) {
         for (int r = 0; r < 27 && !in; ++r) {
           if (r == 13 || !((m >> r) & 1)) continue;
           const int d[3] = {r % 3 - 1, (r / 3) % 3 - 1, r / 9 - 1};
-          bool ok = true, even_facing = true, odd_tang = false;
+          bool ok = true;
           for (int a = 0; a < 3; ++a) {
             if (d[a] < 0 && !((lo >> a) & 1)) ok = false;
             if (d[a] > 0 && !((hi >> a) & 1)) ok = false;
-            if (d[a] != 0 && ((par >> a) & 1)) even_facing = false;
-            if (d[a] == 0 && ((par >> a) & 1)) odd_tang = true;
           }
-          in = ok && (g->Nt ? par != 0 : (even_facing && odd_tang));
+          in = ok && par != 0;   // every detail of the slab, both families
         }
         if (in) t[idx >> 6] |= 1ull << (idx & 63);
       }
