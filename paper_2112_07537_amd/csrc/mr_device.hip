@@ -506,102 +506,81 @@ __device__ __forceinline__ void make_desc(const DevGrid<T>& g, int b, int r, Des
 }
 
 // ------------------------------------------------------------ substitution
-// New value of a point of parity (PX, PY, PZ) (section 2.3, 1D sign of
-// section 2.2.4): minus the non-central taps of the tensor product of G^a
-// over its odd axes, read from the staged region V around element i.  The
-// taps are summed in one fixed order, so every item that computes the point
-// gets the same bits.
-template <typename T, int N, int PX, int PY, int PZ>
-__device__ __forceinline__ T subst_point(const T* V, int i, int sy, int sz) {
-  constexpr int RX = PX ? N - 1 : 0, RY = PY ? N - 1 : 0, RZ = PZ ? N - 1 : 0;
-  // four partial sums (taps in a fixed round-robin order) shorten the
-  // dependent chain; they are added in a fixed order too
-  T acc[4] = {T(0), T(0), T(0), T(0)};
-  int k = 0;
-#pragma unroll
-  for (int oz = -RZ; oz <= RZ; ++oz) {
-    if (oz != 0 && !(oz & 1)) continue;
-#pragma unroll
-    for (int oy = -RY; oy <= RY; ++oy) {
-      if (oy != 0 && !(oy & 1)) continue;
-#pragma unroll
-      for (int ox = -RX; ox <= RX; ++ox) {
-        if (ox != 0 && !(ox & 1)) continue;
-        if (ox == 0 && oy == 0 && oz == 0) continue;
-        constexpr double one = 1.0;
-        const double w = (PZ ? Ga<N>::c(oz) : one) * (PY ? Ga<N>::c(oy) : one) *
-                         (PX ? Ga<N>::c(ox) : one);
-        acc[k & 3] += T(w) * V[i + ox + oy * sy + oz * sz];
-        ++k;
-      }
-    }
-  }
-  return -((acc[0] + acc[1]) + (acc[2] + acc[3]));
-}
-
-// Lattice coordinates of a substitution item along each axis, split by
-// parity: all staged coordinates (lat) and those inside the box (box), as
-// offsets in the staged region.
-struct SubstLattice {
-  int8_t lat[3][2][40];
-  int8_t box[3][2][40];
-  int32_t nlat[3][2], nbox[3][2];
+// Lattice of a substitution item along one axis: the coordinates a box
+// point's chain of stencils can read, i.e. the even ones of [lo - R, hi + R)
+// (nE of them, from e0) followed by the odd ones of [lo, hi) (nO, from o0),
+// R = N - 1.  In this "combined" order the G^a taps of the odd point with
+// odd index i (combined nE + i) are the even points with indices i .. i+N-1.
+struct SubstAxis {
+  int e0, o0, nE, nO, nL;
 };
 
-// Runs fn(li, x, y, z) over the points of one parity class (PX, PY, PZ) of
-// the staged lattice (BOX = false) or of the box (BOX = true); all lanes of
-// a wave work on points of the same class.
-template <int PX, int PY, int PZ, bool BOX, typename Fn>
-__device__ __forceinline__ void for_class(const SubstLattice& L, const int* r0, const int* rs, Fn fn) {
-  const int n0 = BOX ? L.nbox[0][PX] : L.nlat[0][PX];
-  const int n1 = BOX ? L.nbox[1][PY] : L.nlat[1][PY];
-  const int n2 = BOX ? L.nbox[2][PZ] : L.nlat[2][PZ];
+__host__ __device__ __forceinline__ SubstAxis subst_axis(int lo, int hi, int R) {
+  SubstAxis a;
+  const int s = lo - R;
+  a.e0 = s + (s & 1);
+  a.nE = (hi + R - a.e0 + 1) >> 1;
+  a.o0 = lo | 1;
+  a.nO = hi > a.o0 ? (hi - a.o0 + 1) >> 1 : 0;
+  a.nL = a.nE + a.nO;
+  return a;
+}
+
+// Sum over the N taps w_j = G^a(2j - R) of p[j * stride] (the odd offsets
+// -R .. R of the one-axis filter, in a fixed order).
+template <typename T, int N>
+__device__ __forceinline__ T gtaps(const T* p, int stride) {
+  T acc[2] = {T(0), T(0)};
+#pragma unroll
+  for (int j = 0; j < N; ++j) acc[j & 1] += T(Ga<N>::c(2 * j - (N - 1))) * p[j * stride];
+  return acc[0] + acc[1];
+}
+
+// fn(i0, i1, i2) over a box of extents n0 x n1 x n2, i0 fastest, spread over
+// the workgroup.
+template <typename Fn>
+__device__ __forceinline__ void for_box(int n0, int n1, int n2, Fn fn) {
   const int n = n0 * n1 * n2;
   if (n == 0) return;
   Iter3 q(threadIdx.x, blockDim.x, n0, n1);
-  for (int i = threadIdx.x; i < n; i += blockDim.x, q.advance()) {
-    const int qx = BOX ? L.box[0][PX][q.x] : L.lat[0][PX][q.x];
-    const int qy = BOX ? L.box[1][PY][q.y] : L.lat[1][PY][q.y];
-    const int qz = BOX ? L.box[2][PZ][q.z] : L.lat[2][PZ][q.z];
-    fn((qz * rs[1] + qy) * rs[0] + qx, r0[0] + qx, r0[1] + qy, r0[2] + qz);
-  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x, q.advance()) fn(q.x, q.y, q.z);
 }
 
-// One workgroup per substitution item: a box of fine block F's slab points.
-// F's ghost-filled values over the box widened by N-1 points on every axis
-// (the reach of G^a) are staged in LDS: F's own points, same-level
-// neighbours' points and, in coarser regions, F's c->f patches, which hold
-// the refinement of the samples from before the substitution (the patch
-// launch runs first).  A box point's chain of stencils (degree 3 -> 2 -> 1
-// -> 0, one axis per step) only reads points whose coordinate on every axis
-// lies in the box or is even (the lattice), so only those are staged, each
-// with its slab flag from the owning block's slab table (host-built per
-// block: bit lo | hi << 3 | parity << 6 set when a point with that front /
-// back slab range membership and parity lies in one of the block's slabs).
-// Then, degree 1 and then degree 2, every flagged lattice point is replaced
-// in LDS; finally the box's flagged points (degree 3 computed last) are
-// written to the field.  A staged point's odd coordinates lie in the box, so
-// its stencil stays inside the staged region.  With 26-neighbour 2:1 balance
-// no finer region lies within the widened box of a slab.
+// One workgroup per substitution item: a box of fine block F's slab points
+// (section 2.3: a point of degree k, with k odd indices, gets minus the
+// non-central taps of the tensor product of G^a over its odd axes; degree 1
+// first, then 2, then 3, each reading the lower degrees' new values; 1D
+// sign of section 2.2.4).
+//
+// The item stages F's ghost-filled values on the lattice of its box (per
+// axis the even coordinates within N-1 of the box and the odd ones inside
+// it, in the combined order above): F's own points, same-level neighbours'
+// points and, in coarser regions, F's c->f patches, which hold the
+// refinement of the samples from before the substitution (the patch launch
+// runs first).  Each lattice point carries its slab flag from the owning
+// block's slab table (bit lo | hi << 3 | parity << 6 set when a point with
+// that front / back slab range membership and parity lies in one of the
+// block's slabs).  Every flagged lattice point of degree 1 and then 2 is
+// recomputed, and the box's points of degree 3; the tensor sums run as 1D
+// passes (degree 2: along the second odd axis into a temporary, then the
+// first; degree 3: z, y, then x), with the central term left out where the
+// point itself would enter.  Finally the box's flagged points go to the field
+// in natural order.
 //
 // Items run in any order and each writes only its own box (the host cuts a
 // block's slabs into disjoint boxes), but reads points of other boxes, its
-// own block's and its same-level neighbours'.  Every slab point that a box
-// point depends on, in F or in a same-level neighbour (with that
-// neighbour's own coarser regions), is recomputed here from all-even points
-// and points outside every slab, which no item writes; so whether a staged
-// slab value was read before or after its own item wrote it never matters,
-// and the result does not depend on the order of the items.
+// own block's and its same-level neighbours'.  Every slab value a box point
+// depends on is recomputed here from all-even points and points outside
+// every slab, which no item writes; so whether a staged slab value was read
+// before or after its own item wrote it never matters, and the result does
+// not depend on the order of the items.  With 26-neighbour 2:1 balance no
+// finer region lies within the widened box of a slab.
 template <typename T, int N, int NT, int NB>
 __global__ __launch_bounds__(512) void k_subst(DevGrid<T> g, const GItem* __restrict__ items) {
   extern __shared__ unsigned char lds_raw[];
-  T* V = reinterpret_cast<T*>(lds_raw);
   __shared__ Desc desc[27];
   __shared__ uint64_t tab[27][8];   // slab tables of the blocks owning the
                                     // regions at F's level (zero otherwise)
-  __shared__ SubstLattice L;
-  __shared__ int8_t latall[3][40];  // all lattice coordinates per axis
-  __shared__ int32_t nall[3];
   constexpr int R = N - 1;
   constexpr int FL = NT ? N : N - 1;        // front slab [0, FL)
   constexpr int BL = NT ? NB - N + 1 : NB - N + 2;   // back slab [BL, NB)
@@ -619,58 +598,37 @@ __global__ __launch_bounds__(512) void k_subst(DevGrid<T> g, const GItem* __rest
     const bool same = r == 13 || g.poff[(int64_t)F * 27 + r] < 0;
     tab[r][w] = same ? g.stab[(int64_t)o * 8 + w] : 0ull;
   }
-  int r0[3], rs[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    r0[a] = it.lo[a] - R;
-    rs[a] = it.hi[a] - it.lo[a] + 2 * R;
-  }
-  if (tid < 3) {
-    const int a = tid;
-    const int lo = a == 0 ? it.lo[0] : (a == 1 ? it.lo[1] : it.lo[2]);
-    const int hi = a == 0 ? it.hi[0] : (a == 1 ? it.hi[1] : it.hi[2]);
-    int c[2] = {0, 0}, cb[2] = {0, 0}, ca = 0;
-    for (int v = lo - R; v < hi + R; ++v) {
-      const bool inb = v >= lo && v < hi;
-      const int p = v & 1;
-      const int8_t q = int8_t(v - (lo - R));
-      if (inb || !p) {
-        L.lat[a][p][c[p]++] = q;
-        latall[a][ca++] = q;
-      }
-      if (inb) L.box[a][p][cb[p]++] = q;
-    }
-    for (int p = 0; p < 2; ++p) {
-      L.nlat[a][p] = c[p];
-      L.nbox[a][p] = cb[p];
-    }
-    nall[a] = ca;
-  }
-  const int sy = rs[0], sz = rs[0] * rs[1];
-  uint8_t* FLG = reinterpret_cast<uint8_t*>(V + (size_t)sz * rs[2]);
+  const SubstAxis ax = subst_axis(it.lo[0], it.hi[0], R);
+  const SubstAxis ay = subst_axis(it.lo[1], it.hi[1], R);
+  const SubstAxis az = subst_axis(it.lo[2], it.hi[2], R);
+  const int L0 = ax.nL, L1 = ay.nL;
+  const int L01 = L0 * L1;
+  const int nV = L01 * az.nL;
+  T* V = reinterpret_cast<T*>(lds_raw);
+  uint8_t* FLG = reinterpret_cast<uint8_t*>(V + nV);
+  T* TMP = reinterpret_cast<T*>(lds_raw + ((size_t(nV) * (sizeof(T) + 1) + sizeof(T) - 1) /
+                                           sizeof(T)) * sizeof(T));
   __syncthreads();
   {
     // stage the lattice, value and slab flag; U loads in flight per thread
     constexpr int U = 8;
-    const int l0 = nall[0], l1 = nall[1], nl = l0 * l1 * nall[2];
-    Iter3 q(tid, nt, l0, l1);
-    for (int i0 = tid; i0 < nl; i0 += U * nt) {
+    Iter3 q(tid, nt, L0, L1);
+    for (int i0 = tid; i0 < nV; i0 += U * nt) {
       T v[U];
-      int li[U];
       uint8_t fl[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const bool in = i0 + u * nt < nl;
-        const int qx = latall[0][in ? q.x : 0], qy = latall[1][in ? q.y : 0],
-                  qz = latall[2][in ? q.z : 0];
-        const int x = r0[0] + qx, y = r0[1] + qy, z = r0[2] + qz;
+        const bool in = i0 + u * nt < nV;
+        const int cx = in ? q.x : 0, cy = in ? q.y : 0, cz = in ? q.z : 0;
+        const int x = cx < ax.nE ? ax.e0 + 2 * cx : ax.o0 + 2 * (cx - ax.nE);
+        const int y = cy < ay.nE ? ay.e0 + 2 * cy : ay.o0 + 2 * (cy - ay.nE);
+        const int z = cz < az.nE ? az.e0 + 2 * cz : az.o0 + 2 * (cz - az.nE);
         const int rx = x < 0 ? 0 : (x < NB ? 1 : 2);
         const int ry = y < 0 ? 0 : (y < NB ? 1 : 2);
         const int rz = z < 0 ? 0 : (z < NB ? 1 : 2);
         const int r = rx + 3 * ry + 9 * rz;
         const Desc d = desc[r];
         v[u] = (d.patch ? g.patch : g.field)[d.off + x + (int64_t)y * d.sy + (int64_t)z * d.sz];
-        li[u] = (qz * rs[1] + qy) * rs[0] + qx;
         const int lx = x - (rx - 1) * NB, ly = y - (ry - 1) * NB, lz = z - (rz - 1) * NB;
         const int bits = (lx < FL) | ((ly < FL) << 1) | ((lz < FL) << 2) | ((lx >= BL) << 3) |
                          ((ly >= BL) << 4) | ((lz >= BL) << 5) |
@@ -680,48 +638,99 @@ __global__ __launch_bounds__(512) void k_subst(DevGrid<T> g, const GItem* __rest
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (i0 + u * nt < nl) {
-          V[li[u]] = v[u];
-          FLG[li[u]] = fl[u];
+        if (i0 + u * nt < nV) {
+          V[i0 + u * nt] = v[u];
+          FLG[i0 + u * nt] = fl[u];
         }
     }
   }
   __syncthreads();
-  // degree 1, then degree 2, over the staged lattice, in place: degree k
-  // reads only points of lower degree
-  for_class<1, 0, 0, false>(L, r0, rs, [&](int li, int, int, int) {
-    if (FLG[li]) V[li] = subst_point<T, N, 1, 0, 0>(V, li, sy, sz);
+  // degree 1: odd along one axis, the N even neighbours along it
+  for_box(ax.nO, ay.nE, az.nE, [&](int i, int j, int k) {
+    const int row = (k * L1 + j) * L0;
+    const int p = row + ax.nE + i;
+    if (FLG[p]) V[p] = -gtaps<T, N>(V + row + i, 1);
   });
-  for_class<0, 1, 0, false>(L, r0, rs, [&](int li, int, int, int) {
-    if (FLG[li]) V[li] = subst_point<T, N, 0, 1, 0>(V, li, sy, sz);
+  for_box(ax.nE, ay.nO, az.nE, [&](int i, int j, int k) {
+    const int p = (k * L1 + ay.nE + j) * L0 + i;
+    if (FLG[p]) V[p] = -gtaps<T, N>(V + (k * L1 + j) * L0 + i, L0);
   });
-  for_class<0, 0, 1, false>(L, r0, rs, [&](int li, int, int, int) {
-    if (FLG[li]) V[li] = subst_point<T, N, 0, 0, 1>(V, li, sy, sz);
-  });
-  __syncthreads();
-  for_class<1, 1, 0, false>(L, r0, rs, [&](int li, int, int, int) {
-    if (FLG[li]) V[li] = subst_point<T, N, 1, 1, 0>(V, li, sy, sz);
-  });
-  for_class<1, 0, 1, false>(L, r0, rs, [&](int li, int, int, int) {
-    if (FLG[li]) V[li] = subst_point<T, N, 1, 0, 1>(V, li, sy, sz);
-  });
-  for_class<0, 1, 1, false>(L, r0, rs, [&](int li, int, int, int) {
-    if (FLG[li]) V[li] = subst_point<T, N, 0, 1, 1>(V, li, sy, sz);
+  for_box(ax.nE, ay.nE, az.nO, [&](int i, int j, int k) {
+    const int p = ((az.nE + k) * L1 + j) * L0 + i;
+    if (FLG[p]) V[p] = -gtaps<T, N>(V + (k * L1 + j) * L0 + i, L01);
   });
   __syncthreads();
-  // the box's slab points to the field, degree 3 computed here
+  // degree 2: the tensor sum along the second odd axis into a temporary,
+  // without the central term where that would be the point itself
+  T* Txy = TMP;                                   // [nE_z][nO_y][L0]
+  T* Txz = Txy + az.nE * ay.nO * L0;              // [nO_z][nE_y][L0]
+  T* Tyz = Txz + az.nO * ay.nE * L0;              // [nO_z][L1][nE_x]
+  for_box(L0, ay.nO, az.nE, [&](int c, int j, int k) {
+    T v = gtaps<T, N>(V + (k * L1 + j) * L0 + c, L0);
+    if (c < ax.nE) v += V[(k * L1 + ay.nE + j) * L0 + c];
+    Txy[(k * ay.nO + j) * L0 + c] = v;
+  });
+  for_box(L0, ay.nE, az.nO, [&](int c, int j, int k) {
+    T v = gtaps<T, N>(V + (k * L1 + j) * L0 + c, L01);
+    if (c < ax.nE) v += V[((az.nE + k) * L1 + j) * L0 + c];
+    Txz[(k * ay.nE + j) * L0 + c] = v;
+  });
+  for_box(ax.nE, L1, az.nO, [&](int i, int c, int k) {
+    T v = gtaps<T, N>(V + (k * L1 + c) * L0 + i, L01);
+    if (c < ay.nE) v += V[((az.nE + k) * L1 + c) * L0 + i];
+    Tyz[(k * L1 + c) * ax.nE + i] = v;
+  });
+  __syncthreads();
+  // degree 2: then along the first odd axis (the temporary's odd entry holds
+  // the other taps of the point's own column)
+  for_box(ax.nO, ay.nO, az.nE, [&](int i, int j, int k) {
+    const int p = (k * L1 + ay.nE + j) * L0 + ax.nE + i;
+    const T* t = Txy + (k * ay.nO + j) * L0;
+    if (FLG[p]) V[p] = -(t[ax.nE + i] + gtaps<T, N>(t + i, 1));
+  });
+  for_box(ax.nO, ay.nE, az.nO, [&](int i, int j, int k) {
+    const int p = ((az.nE + k) * L1 + j) * L0 + ax.nE + i;
+    const T* t = Txz + (k * ay.nE + j) * L0;
+    if (FLG[p]) V[p] = -(t[ax.nE + i] + gtaps<T, N>(t + i, 1));
+  });
+  for_box(ax.nE, ay.nO, az.nO, [&](int i, int j, int k) {
+    const int p = ((az.nE + k) * L1 + ay.nE + j) * L0 + i;
+    const T* t = Tyz + k * L1 * ax.nE + i;
+    if (FLG[p]) V[p] = -(t[(ay.nE + j) * ax.nE] + gtaps<T, N>(t + j * ax.nE, ax.nE));
+  });
+  __syncthreads();
+  // degree 3: z, then y, then x; the central term is left out of the z sum
+  // at the odd-odd (x, y) columns, which only their own point reads
+  T* A = TMP;                                     // [nO_z][L1][L0]
+  T* B = A + az.nO * L01;                         // [nO_z][nO_y][L0]
+  for_box(L0, L1, az.nO, [&](int cx, int cy, int k) {
+    T v = gtaps<T, N>(V + (k * L1 + cy) * L0 + cx, L01);
+    if (cx < ax.nE || cy < ay.nE) v += V[((az.nE + k) * L1 + cy) * L0 + cx];
+    A[(k * L1 + cy) * L0 + cx] = v;
+  });
+  __syncthreads();
+  for_box(L0, ay.nO, az.nO, [&](int c, int j, int k) {
+    const T* a = A + k * L01 + c;
+    B[(k * ay.nO + j) * L0 + c] = a[(ay.nE + j) * L0] + gtaps<T, N>(a + j * L0, L0);
+  });
+  __syncthreads();
+  for_box(ax.nO, ay.nO, az.nO, [&](int i, int j, int k) {
+    const int p = ((az.nE + k) * L1 + ay.nE + j) * L0 + ax.nE + i;
+    const T* b = B + (k * ay.nO + j) * L0;
+    if (FLG[p]) V[p] = -(b[ax.nE + i] + gtaps<T, N>(b + i, 1));
+  });
+  __syncthreads();
+  // the box's slab points to the field, in natural order
   T* fb = g.field + (int64_t)F * (NB * NB * NB);
-  auto put = [&](int li, int x, int y, int z) {
-    if (FLG[li]) fb[(z * NB + y) * NB + x] = V[li];
-  };
-  for_class<1, 0, 0, true>(L, r0, rs, put);
-  for_class<0, 1, 0, true>(L, r0, rs, put);
-  for_class<0, 0, 1, true>(L, r0, rs, put);
-  for_class<1, 1, 0, true>(L, r0, rs, put);
-  for_class<1, 0, 1, true>(L, r0, rs, put);
-  for_class<0, 1, 1, true>(L, r0, rs, put);
-  for_class<1, 1, 1, true>(L, r0, rs, [&](int li, int x, int y, int z) {
-    if (FLG[li]) fb[(z * NB + y) * NB + x] = subst_point<T, N, 1, 1, 1>(V, li, sy, sz);
+  const int b0 = it.hi[0] - it.lo[0], b1 = it.hi[1] - it.lo[1], b2 = it.hi[2] - it.lo[2];
+  for_box(b0, b1, b2, [&](int i, int j, int k) {
+    const int x = it.lo[0] + i, y = it.lo[1] + j, z = it.lo[2] + k;
+    if (((x | y | z) & 1) == 0) return;
+    const int cx = (x & 1) ? ax.nE + ((x - ax.o0) >> 1) : (x - ax.e0) >> 1;
+    const int cy = (y & 1) ? ay.nE + ((y - ay.o0) >> 1) : (y - ay.e0) >> 1;
+    const int cz = (z & 1) ? az.nE + ((z - az.o0) >> 1) : (z - az.e0) >> 1;
+    const int p = (cz * L1 + cy) * L0 + cx;
+    if (FLG[p]) fb[(z * NB + y) * NB + x] = V[p];
   });
 }
 

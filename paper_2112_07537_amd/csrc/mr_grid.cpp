@@ -427,12 +427,26 @@ static const int kLdsBudgetRefine = 20 * 1024;
 static const int kLdsBudgetRestrict = 24 * 1024;
 static const int kLdsBudgetSubst = 60 * 1024;
 
-// LDS of a substitution item: its box widened by N-1 points on every axis,
-// one value and one flag byte per point.
+// LDS of a substitution item (k_subst): the lattice of its box (per axis
+// the even coordinates within N-1 of the box and the odd ones inside it),
+// one value and one flag byte per point, then the larger of the degree-2
+// and degree-3 temporaries of the separable tensor sums.
 static int subst_lds(const GItem& it, int N, size_t esz) {
-  size_t v = esz + 1;
-  for (int a = 0; a < 3; ++a) v *= size_t(it.hi[a] - it.lo[a] + 2 * (N - 1));
-  return int(v);
+  const int R = N - 1;
+  int nE[3], nO[3], nL[3];
+  for (int a = 0; a < 3; ++a) {
+    const int lo = it.lo[a], hi = it.hi[a];
+    const int s = lo - R, e0 = s + (s & 1), o0 = lo | 1;
+    nE[a] = (hi + R - e0 + 1) >> 1;
+    nO[a] = hi > o0 ? (hi - o0 + 1) >> 1 : 0;
+    nL[a] = nE[a] + nO[a];
+  }
+  const size_t nV = size_t(nL[0]) * nL[1] * nL[2];
+  const size_t t2 = size_t(nE[2]) * nO[1] * nL[0] + size_t(nO[2]) * nE[1] * nL[0] +
+                    size_t(nO[2]) * nL[1] * nE[0];
+  const size_t t3 = size_t(nO[2]) * nL[1] * nL[0] + size_t(nO[2]) * nO[1] * nL[0];
+  const size_t head = (nV * (esz + 1) + esz - 1) / esz * esz;
+  return int(head + std::max(t2, t3) * esz);
 }
 
 // Split a box along its longest axis until the LDS estimate fits the budget.
