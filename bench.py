@@ -22,6 +22,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2112_07537_amd import autotune as at  # noqa: E402
 from paper_2112_07537_amd import mr  # noqa: E402
 from paper_2112_07537_amd import workloads as wl  # noqa: E402
 
@@ -41,11 +42,11 @@ def log(*a):
 T0 = time.time()
 
 
-def make_grid(cfg, prec=None, exec_mode=0, max_blocks=150000, tree=None):
+def make_grid(cfg, prec=None, exec_mode=0, max_blocks=150000, tree=None, n_fields=1):
     g = mr.Grid(cfg["nb"], cfg["N"], cfg["Nt"], fd_order=cfg["fd"], level_min=cfg["level_min"],
                 level_max=cfg["level_max"], prec=prec or cfg["prec"],
                 eps_refine=cfg["eps_refine"], eps_coarsen=cfg["eps_coarsen"],
-                exec_mode=exec_mode, max_blocks=max_blocks)
+                exec_mode=exec_mode, max_blocks=max_blocks, n_fields=n_fields)
     if tree is not None or cfg.get("tree"):
         g.set_tree(tree if tree is not None else wl.tree_of(cfg))
         g.sample_ic(*cfg["ic"])
@@ -94,6 +95,27 @@ def fused_loop(g, cfg, steps):
         g.details_rk3_step_async(dt, vel)
     g.sync()
     return time.perf_counter() - t0, points
+
+
+def plain_step(g, cfg):
+    """One RK3 step plus a detail pass on a plain-mode grid (one launch per
+    block per operation), as three mr_stage calls (fields u, A, B: the
+    SSP-RK3 stages of mr_rk3_step) and mr_details, each synchronised and
+    logged: at 60k leaves in FP64 a stage takes tens of seconds."""
+    kind, p = wl.velocity_spec(cfg["vel"])
+    vel = mr.velocity(kind, *p)
+    dt = g.cfl_dt(vel, cfg["cfl"])
+    g.sync()
+    t0 = time.perf_counter()
+    for i, (y, out, a, b) in enumerate(((0, 1, 0.0, 1.0), (1, 2, 0.75, 0.25),
+                                        (2, 0, 1.0 / 3.0, 2.0 / 3.0))):
+        g.stage(y, 0, out, a, b, 1.0, dt, vel)
+        g.sync()
+        log("  plain stage %d done at %.1f s" % (i + 1, time.perf_counter() - t0))
+    g.details()
+    t = time.perf_counter() - t0
+    log("  plain detail pass done at %.1f s" % t)
+    return t, g.n_blocks() * cfg["nb"] ** 3
 
 
 def host_info():
@@ -299,7 +321,6 @@ def main():
     ap.add_argument("--config", default="c5")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--breakdown-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 2 GiB device copy (counter calibration)")
@@ -322,6 +343,19 @@ def main():
     cfg = getattr(wl, args.config)()
     log("config", cfg["name"])
     g = make_grid(cfg)
+    # launch-shape knobs from the autotuner's cache, if it has this
+    # configuration: time the defaults first, for the gain
+    arch = at.gpu_arch()
+    entry = at.load().get(at.cache_key(arch, cfg))
+    tuning = {"arch": arch, "knobs": g.get_tuning(), "source": "defaults"}
+    if entry:
+        step_loop(g, cfg, args.warmup)
+        td, pd, _, _ = step_loop(g, cfg, args.steps)
+        tuning["ms_per_step_defaults"] = 1e3 * td / args.steps
+        g.set_tuning(**entry["knobs"])
+        tuning.update(knobs=g.get_tuning(), source="paper_2112_07537_amd/tuning.json")
+        log("defaults: %.3f ms/step; tuned knobs %s" % (tuning["ms_per_step_defaults"],
+                                                        tuning["knobs"]))
     n_blocks = g.n_blocks()
     n_pts = n_blocks * cfg["nb"] ** 3
     ts = g.tree_stats()
@@ -338,6 +372,8 @@ def main():
     value = points / t
     ms = 1e3 * t / args.steps
     log("batched %s: %.3f ms/step, %.4g points/s" % (cfg["prec"], ms, value))
+    if "ms_per_step_defaults" in tuning:
+        tuning["gain_vs_defaults"] = tuning["ms_per_step_defaults"] / ms
 
     # -- per-kernel breakdown: HIP events around every launch, recording
     # started after a warm-up step
@@ -388,6 +424,7 @@ def main():
         # -- the same steps with each RK3 step replayed as one captured hipGraph
         log("fp32 hipGraph path")
         gg = make_grid(cfg, exec_mode=2, tree=tree)
+        gg.set_tuning(**tuning["knobs"])
         step_loop(gg, cfg, args.warmup)
         tg, pg, _, _ = step_loop(gg, cfg, args.steps)
         extra["graph_points_per_s"] = pg / tg
@@ -397,6 +434,9 @@ def main():
         # -- FP64 batched path (same kernels in FP64, same tree)
         log("fp64 batched path")
         gb = make_grid(cfg, prec="f64", exec_mode=0, tree=tree)
+        e64 = at.load().get(at.cache_key(arch, cfg, "f64"))
+        if e64:
+            gb.set_tuning(**e64["knobs"])
         step_loop(gb, cfg, 1)
         tb64, pb, _, _ = step_loop(gb, cfg, max(2, args.steps // 4))
         extra["fp64_batched_points_per_s"] = pb / tb64
@@ -404,9 +444,8 @@ def main():
         gb.close()
         # -- FP64 plain path (one launch per block per operation, no graph)
         log("fp64 plain path")
-        gp = make_grid(cfg, prec="f64", exec_mode=1, tree=tree)
-        step_loop(gp, cfg, 1)
-        tp, pp, _, _ = step_loop(gp, cfg, args.plain_steps)
+        gp = make_grid(cfg, prec="f64", exec_mode=1, tree=tree, n_fields=3)
+        tp, pp = plain_step(gp, cfg)
         extra["fp64_plain_points_per_s"] = pp / tp
         extra["speedup_vs_fp64_plain"] = value / extra["fp64_plain_points_per_s"]
         log("fp64 plain: %.4g points/s" % extra["fp64_plain_points_per_s"])
@@ -436,6 +475,7 @@ def main():
                      "dominant_kernel": dom[0],
                      "dominant_kernel_ms_per_step": dom[1]["ms_per_step"] if dom[1] else None},
         "kernels": kernels,
+        "tuning": tuning,
         "instrumented_ms_per_step": ms_instr,
         "cpu_baseline": cpu,
     }

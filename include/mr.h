@@ -119,6 +119,22 @@ typedef struct {
   int64_t n_blocks;   /* leaves after adaptation                          */
 } mr_adapt_stats;
 
+/* Launch-shape knobs of the ghost kernels (no effect on results beyond
+ * the rounding order of restriction tiles): the LDS budget in bytes that a
+ * c->f, f->c or substitution work item is tiled to (each item's box is
+ * halved along its longest axis until its LDS fits; a launch reserves its
+ * largest item's LDS per workgroup, so smaller tiles let more workgroups
+ * share a CU), and the substitution workgroup size (256 or 512 threads).
+ * 0 in a field of mr_set_tuning keeps the current value.  Budgets must lie
+ * in [4096, 65536]. */
+typedef struct {
+  int32_t lds_refine;     /* c->f items, default 20480                       */
+  int32_t lds_restrict;   /* f->c items, default 24576                       */
+  int32_t lds_subst;      /* substitution items, default 61440               */
+  int32_t subst_threads;  /* 256 or 512, default 512                         */
+  int32_t reserved[4];
+} mr_tuning;
+
 /* Create a grid (the block-structured grid of section 2.2 with the
  * adaptation parameters of section 2.2.5).  hip_stream: a hipStream_t, or
  * NULL for a private stream owned by the grid.  dev_pool: NULL (the library
@@ -284,6 +300,20 @@ mr_status mr_moments(mr_grid* g, int32_t field, double out[4]);
  * the field sampled on the finest level): out[0] = max |phi - f|,
  * out[1] = sqrt(sum h^3 (phi - f)^2).  Synchronises. */
 mr_status mr_ic_error(mr_grid* g, int32_t field, const mr_ic* ic, double out[2]);
+
+/* Set the launch-shape knobs (see mr_tuning) and rebuild the work lists of
+ * the current tree; MR_EINVAL for values out of range (nothing changes).
+ * An autotuner times them per configuration; results do not depend on them
+ * except for the rounding order of f->c sums.  Synchronises. */
+mr_status mr_set_tuning(mr_grid* g, const mr_tuning* t);
+
+/* The knobs in effect. */
+mr_status mr_get_tuning(mr_grid* g, mr_tuning* t);
+
+/* Architecture name of the current HIP device (e.g. "gfx950"), the key
+ * under which tuned knobs are cached; written NUL-terminated into out
+ * (host memory of n bytes). */
+mr_status mr_device_arch(char* out, size_t n);
 
 /* Kernel timing with HIP events recorded on the grid's stream around each
  * launch of the named kernel family ("rhs", "details", "ghost_refine",

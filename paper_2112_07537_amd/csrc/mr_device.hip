@@ -575,8 +575,8 @@ __device__ __forceinline__ void for_box(int n0, int n1, int n2, Fn fn) {
 // before or after its own item wrote it never matters, and the result does
 // not depend on the order of the items.  With 26-neighbour 2:1 balance no
 // finer region lies within the widened box of a slab.
-template <typename T, int N, int NT, int NB>
-__global__ __launch_bounds__(512) void k_subst(DevGrid<T> g, const GItem* __restrict__ items) {
+template <typename T, int N, int NT, int NB, int TPB>
+__global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __restrict__ items) {
   extern __shared__ unsigned char lds_raw[];
   __shared__ Desc desc[27];
   __shared__ uint64_t tab[27][8];   // slab tables of the blocks owning the
@@ -1741,21 +1741,28 @@ void launch_gview(bool f32, const void* dg, Wavelet w, const GItem* items, int n
 }
 
 template <typename T, int NB>
-static void subst_nb(const DevGrid<T>& g, Wavelet w, const GItem* items, int n, int lds, hipStream_t s) {
-  MR_WAVELET_SWITCH(w, MR_LAUNCH((k_subst<T, N_, NT_, NB>), dim3(n), dim3(512), lds, s, g, items));
+static void subst_nb(const DevGrid<T>& g, Wavelet w, const GItem* items, int n, int lds,
+                     int threads, hipStream_t s) {
+  if (threads == 256)
+    MR_WAVELET_SWITCH(w, MR_LAUNCH((k_subst<T, N_, NT_, NB, 256>), dim3(n), dim3(256), lds, s, g,
+                                   items));
+  else
+    MR_WAVELET_SWITCH(w, MR_LAUNCH((k_subst<T, N_, NT_, NB, 512>), dim3(n), dim3(512), lds, s, g,
+                                   items));
 }
 template <typename T>
-static void subst_t(const void* dg, Wavelet w, const GItem* items, int n, int lds, hipStream_t s) {
+static void subst_t(const void* dg, Wavelet w, const GItem* items, int n, int lds, int threads,
+                    hipStream_t s) {
   const DevGrid<T>& g = *static_cast<const DevGrid<T>*>(dg);
-  if (g.nb == 8) subst_nb<T, 8>(g, w, items, n, lds, s);
-  else if (g.nb == 16) subst_nb<T, 16>(g, w, items, n, lds, s);
-  else subst_nb<T, 24>(g, w, items, n, lds, s);
+  if (g.nb == 8) subst_nb<T, 8>(g, w, items, n, lds, threads, s);
+  else if (g.nb == 16) subst_nb<T, 16>(g, w, items, n, lds, threads, s);
+  else subst_nb<T, 24>(g, w, items, n, lds, threads, s);
 }
 void launch_subst(bool f32, const void* dg, Wavelet w, const GItem* items, int n, int lds,
-                  hipStream_t s) {
+                  int threads, hipStream_t s) {
   if (n <= 0) return;
-  if (f32) subst_t<float>(dg, w, items, n, lds, s);
-  else subst_t<double>(dg, w, items, n, lds, s);
+  if (f32) subst_t<float>(dg, w, items, n, lds, threads, s);
+  else subst_t<double>(dg, w, items, n, lds, threads, s);
 }
 
 template <typename T, int NB>

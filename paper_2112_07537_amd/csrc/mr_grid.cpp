@@ -176,6 +176,16 @@ static double now_ms() {
 
 using namespace mr;
 
+// Defaults of the launch-shape knobs (mr_tuning).  LDS per work item is
+// bounded by tiling: every workgroup of a launch reserves the largest item's
+// LDS, so smaller tiles raise the number of resident workgroups.  The c->f
+// and substitution values do not depend on the tiling; the rounding order of
+// an f->c sum follows its tile's thinnest axis.
+static const int kLdsBudgetRefine = 20 * 1024;
+static const int kLdsBudgetRestrict = 24 * 1024;
+static const int kLdsBudgetSubst = 60 * 1024;
+static const int kSubstThreads = 512;
+
 struct mr_grid {
   mr_config cfg{};
   hipStream_t stream = nullptr;
@@ -189,6 +199,7 @@ struct mr_grid {
   std::vector<DevBuf> backup;   // fields at the start of an mr_adapt call
   bool f32 = false;
   int nb = 16, N = 4, Nt = 0, G = 2, Dw = 4;
+  mr_tuning tune{kLdsBudgetRefine, kLdsBudgetRestrict, kLdsBudgetSubst, kSubstThreads, {0, 0, 0, 0}};
   int Ef = 0, Eb = 0;
   size_t esz = 8;
   // tree
@@ -418,14 +429,6 @@ static int rview_lds(const RItem& it, int H, size_t esz) {
   return int(esz * (size_t(qs[n]) * xs[a1] * xs[a2] + size_t(qs[n]) * qs[a1] * xs[a2]));
 }
 
-// LDS per work item is bounded by tiling: every workgroup of a launch
-// reserves the largest item's LDS, so smaller tiles raise the number of
-// resident workgroups.  The budgets were chosen by timing the c->f and f->c
-// launches on MI355X (20 KB and 24 KB beat 16, 32 and 48 KB); the c->f
-// values do not depend on the tiling, and the f->c tiling is fixed.
-static const int kLdsBudgetRefine = 20 * 1024;
-static const int kLdsBudgetRestrict = 24 * 1024;
-static const int kLdsBudgetSubst = 60 * 1024;
 
 // LDS of a substitution item (k_subst): the lattice of its box (per axis
 // the even coordinates within N-1 of the box and the odd ones inside it),
@@ -605,7 +608,7 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
               if (g->leaves[it.fblk].L != Lb + 1)
                 return false;
               P.pts += box_size(it.lo, it.hi);
-              push_tiled(P.r, it, rlds, kLdsBudgetRestrict);
+              push_tiled(P.r, it, rlds, g->tune.lds_restrict);
             }
       }
     }
@@ -640,7 +643,7 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
           pt.lo[c] = lo[c];
           pt.hi[c] = hi[c];
         }
-        push_tiled(P.g, pt, glds, kLdsBudgetRefine);
+        push_tiled(P.g, pt, glds, g->tune.lds_refine);
       }
     // Overlapping slabs (two faces meet along an edge) are cut into disjoint
     // boxes, so each point is written by exactly one item; the kernel decides
@@ -656,7 +659,7 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
         }
         acc.insert(acc.end(), pieces.begin(), pieces.end());
       }
-      for (const GItem& pc : acc) push_tiled(P.s, pc, slds, kLdsBudgetSubst);
+      for (const GItem& pc : acc) push_tiled(P.s, pc, slds, g->tune.lds_subst);
     }
     return true;
   };
@@ -975,9 +978,10 @@ static void ghost_fill(mr_grid* g, void* field, Lists& L, void* patch = nullptr)
   if (ns) {
     prof_begin(g, 4, &a, &b, !plain);
     if (plain) {
-      for (int i = 0; i < ns; ++i) launch_subst(g->f32, v.raw, w, si + i, 1, L.lds_s, g->stream);
+      for (int i = 0; i < ns; ++i)
+        launch_subst(g->f32, v.raw, w, si + i, 1, L.lds_s, g->tune.subst_threads, g->stream);
     } else {
-      launch_subst(g->f32, v.raw, w, si, ns, L.lds_s, g->stream);
+      launch_subst(g->f32, v.raw, w, si, ns, L.lds_s, g->tune.subst_threads, g->stream);
     }
     prof_end(g, 4, a, b, !plain, L.out_points);
   }
@@ -1961,6 +1965,47 @@ mr_status mr_stage(mr_grid* g, int32_t y, int32_t un, int32_t out, double a_un, 
     return fail(MR_EINVAL, "non-finite stage coefficient");
   ghost_fill(g, g->fields[y].p, g->stage);
   rhs_stage(g, g->fields[y].p, g->fields[un].p, g->fields[out].p, a_un, b, dt, vd, nullptr, c_y);
+  return MR_OK;
+}
+
+mr_status mr_set_tuning(mr_grid* g, const mr_tuning* t) {
+  if (!g || !t) return fail(MR_EINVAL, "null argument");
+  mr_tuning n = g->tune;
+  const int32_t* in[3] = {&t->lds_refine, &t->lds_restrict, &t->lds_subst};
+  int32_t* out[3] = {&n.lds_refine, &n.lds_restrict, &n.lds_subst};
+  for (int k = 0; k < 3; ++k) {
+    if (*in[k] == 0) continue;
+    if (*in[k] < 4096 || *in[k] > 65536) return fail(MR_EINVAL, "LDS budget out of [4096, 65536]");
+    *out[k] = *in[k];
+  }
+  if (t->subst_threads != 0) {
+    if (t->subst_threads != 256 && t->subst_threads != 512)
+      return fail(MR_EINVAL, "subst_threads must be 256 or 512");
+    n.subst_threads = t->subst_threads;
+  }
+  g->tune = n;
+  if (!g->leaves.empty()) {
+    HIPCHK(hipStreamSynchronize(g->stream));
+    return commit_tree(g);
+  }
+  return MR_OK;
+}
+
+mr_status mr_device_arch(char* out, size_t n) {
+  if (!out || n == 0) return fail(MR_EINVAL, "null argument");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  std::string a(prop.gcnArchName);
+  a = a.substr(0, a.find(':'));
+  std::snprintf(out, n, "%s", a.c_str());
+  return MR_OK;
+}
+
+mr_status mr_get_tuning(mr_grid* g, mr_tuning* t) {
+  if (!g || !t) return fail(MR_EINVAL, "null argument");
+  *t = g->tune;
   return MR_OK;
 }
 

@@ -103,8 +103,8 @@ struct Wavelet {
 
 void launch_gview(bool f32, const void* dg, Wavelet w, const GItem* items, int n_items,
                   int lds_bytes, hipStream_t s);
-void launch_subst(bool f32, const void* dg, Wavelet w, const GItem* items, int n_items,
-                  int lds_bytes, hipStream_t s);
+void launch_subst(bool f32, const void* dg, Wavelet w, const GItem* items, int n, int lds,
+                  int threads, hipStream_t s);
 void launch_cell_tables(bool f32, const void* dg, int n_blocks, hipStream_t s);
 void launch_rview(bool f32, const void* dg, Wavelet w, const RItem* items, int n_items,
                   int lds, int maxq, hipStream_t s);

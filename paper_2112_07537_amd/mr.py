@@ -26,6 +26,12 @@ class mr_config(C.Structure):
                 ("eps_coarsen", C.c_double), ("max_blocks", C.c_int64)]
 
 
+class mr_tuning(C.Structure):
+    _fields_ = [("lds_refine", C.c_int32), ("lds_restrict", C.c_int32),
+                ("lds_subst", C.c_int32), ("subst_threads", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
+
+
 class mr_velocity(C.Structure):
     _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("p", C.c_double * 8)]
 
@@ -69,6 +75,9 @@ def load():
         "mr_set_thresholds": [P, C.c_double, C.c_double],
         "mr_ic_error": [P, C.c_int32, C.POINTER(mr_ic), P],
         "mr_adapt_flags": [P, P, C.POINTER(mr_adapt_stats)],
+        "mr_set_tuning": [P, C.POINTER(mr_tuning)],
+        "mr_get_tuning": [P, C.POINTER(mr_tuning)],
+        "mr_device_arch": [C.c_char_p, C.c_size_t],
         "mr_details_rk3_step": [P, C.c_int32, C.c_double, C.POINTER(mr_velocity), P, C.c_int32],
         "mr_cfl_dt": [P, C.POINTER(mr_velocity), C.c_double, C.POINTER(C.c_double)],
         "mr_block_meta": [P, C.c_int64, C.POINTER(C.c_int64), P, P],
@@ -108,6 +117,13 @@ def _check(code):
 
 def _ptr(a):
     return C.c_void_p(a.ctypes.data)
+
+
+def device_arch():
+    """mr_device_arch: the current HIP device's architecture name."""
+    buf = C.create_string_buffer(64)
+    _check(lib().mr_device_arch(buf, 64))
+    return buf.value.decode()
 
 
 def velocity(kind, *p):
@@ -246,6 +262,22 @@ class Grid:
     def rhs(self, y, out, vel):
         """L(y) into field `out` (mr_stage with a_un = 0, b = 1, c_y = 0, dt = 1)."""
         self.stage(y, y, out, 0.0, 1.0, 0.0, 1.0, vel)
+
+    TUNING_KEYS = ("lds_refine", "lds_restrict", "lds_subst", "subst_threads")
+
+    def set_tuning(self, **kw):
+        """mr_set_tuning: launch-shape knobs (mr_tuning fields; omitted = keep)."""
+        t = mr_tuning()
+        for k, v in kw.items():
+            if k not in self.TUNING_KEYS:
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        _check(lib().mr_set_tuning(self._h, C.byref(t)))
+
+    def get_tuning(self):
+        t = mr_tuning()
+        _check(lib().mr_get_tuning(self._h, C.byref(t)))
+        return {k: int(getattr(t, k)) for k in self.TUNING_KEYS}
 
     def set_thresholds(self, eps_refine, eps_coarsen):
         _check(lib().mr_set_thresholds(self._h, eps_refine, eps_coarsen))

@@ -90,3 +90,19 @@ def test_validation_errors_without_device(lib):
     f.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.c_int32]
     f.restype = C.c_int32
     assert f(None, 0, 0.1, None, None, 1) == mr.MR_EINVAL
+
+
+def test_tuning_cache_format():
+    """The autotuner's cache: keys (arch/nb/wavelet/fd/prec) map to knob sets
+    of the mr_tuning fields within the accepted ranges."""
+    from paper_2112_07537_amd import autotune as at
+    from paper_2112_07537_amd import mr as m
+    entries = at.load()
+    for key, e in entries.items():
+        arch, nb, w, fd, prec = key.split("/")
+        assert arch.startswith("gfx") and nb.startswith("nb") and w.startswith("w")
+        assert fd.startswith("fd") and prec in ("f32", "f64")
+        assert set(e["knobs"]) == set(m.Grid.TUNING_KEYS)
+        for k in ("lds_refine", "lds_restrict", "lds_subst"):
+            assert 4096 <= e["knobs"][k] <= 65536
+        assert e["knobs"]["subst_threads"] in (256, 512)
