@@ -575,18 +575,28 @@ __device__ __forceinline__ void for_box(int n0, int n1, int n2, Fn fn) {
 // before or after its own item wrote it never matters, and the result does
 // not depend on the order of the items.  With 26-neighbour 2:1 balance no
 // finer region lies within the widened box of a slab.
+// a * b + c for non-negative operands below 2^24 (full-rate 24-bit multiply)
+__device__ __forceinline__ int imad24(int a, int b, int c) { return int(__umul24(a, b)) + c; }
+
 template <typename T, int N, int NT, int NB, int TPB>
 __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __restrict__ items) {
   extern __shared__ unsigned char lds_raw[];
   __shared__ Desc desc[27];
   __shared__ uint64_t tab[27][8];   // slab tables of the blocks owning the
                                     // regions at F's level (zero otherwise)
+  // per axis and combined lattice index: coordinate relative to F (bits
+  // 0-7, +64), region (bits 8-9), the point's front / back slab membership
+  // and parity in the block holding it (bits 10-12: front, back, odd)
+  __shared__ int32_t lut[3][32];
   constexpr int R = N - 1;
   constexpr int FL = NT ? N : N - 1;        // front slab [0, FL)
   constexpr int BL = NT ? NB - N + 1 : NB - N + 2;   // back slab [BL, NB)
   const GItem it = items[xcd_item(blockIdx.x, gridDim.x)];
   const int F = it.blk;
   const int tid = threadIdx.x, nt = blockDim.x;
+  const SubstAxis ax = subst_axis(it.lo[0], it.hi[0], R);
+  const SubstAxis ay = subst_axis(it.lo[1], it.hi[1], R);
+  const SubstAxis az = subst_axis(it.lo[2], it.hi[2], R);
   if (tid < 27) make_desc(g, F, tid, desc[tid]);
   if (tid < 27 * 8) {
     const int r = tid >> 3, w = tid & 7;
@@ -598,9 +608,16 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
     const bool same = r == 13 || g.poff[(int64_t)F * 27 + r] < 0;
     tab[r][w] = same ? g.stab[(int64_t)o * 8 + w] : 0ull;
   }
-  const SubstAxis ax = subst_axis(it.lo[0], it.hi[0], R);
-  const SubstAxis ay = subst_axis(it.lo[1], it.hi[1], R);
-  const SubstAxis az = subst_axis(it.lo[2], it.hi[2], R);
+  if (tid < 96) {
+    const int a = tid >> 5, c = tid & 31;
+    const SubstAxis& s = a == 0 ? ax : (a == 1 ? ay : az);
+    if (c < s.nL) {
+      const int v = c < s.nE ? s.e0 + 2 * c : s.o0 + 2 * (c - s.nE);
+      const int rg = v < 0 ? 0 : (v < NB ? 1 : 2);
+      const int l = v - (rg - 1) * NB;
+      lut[a][c] = (v + 64) | (rg << 8) | (int(l < FL) << 10) | (int(l >= BL) << 11) | ((v & 1) << 12);
+    }
+  }
   const int L0 = ax.nL, L1 = ay.nL;
   const int L01 = L0 * L1;
   const int nV = L01 * az.nL;
@@ -619,20 +636,15 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool in = i0 + u * nt < nV;
-        const int cx = in ? q.x : 0, cy = in ? q.y : 0, cz = in ? q.z : 0;
-        const int x = cx < ax.nE ? ax.e0 + 2 * cx : ax.o0 + 2 * (cx - ax.nE);
-        const int y = cy < ay.nE ? ay.e0 + 2 * cy : ay.o0 + 2 * (cy - ay.nE);
-        const int z = cz < az.nE ? az.e0 + 2 * cz : az.o0 + 2 * (cz - az.nE);
-        const int rx = x < 0 ? 0 : (x < NB ? 1 : 2);
-        const int ry = y < 0 ? 0 : (y < NB ? 1 : 2);
-        const int rz = z < 0 ? 0 : (z < NB ? 1 : 2);
-        const int r = rx + 3 * ry + 9 * rz;
+        const int ex = lut[0][in ? q.x : 0], ey = lut[1][in ? q.y : 0], ez = lut[2][in ? q.z : 0];
+        const int r = ((ex >> 8) & 3) + 3 * ((ey >> 8) & 3) + 9 * ((ez >> 8) & 3);
         const Desc d = desc[r];
-        v[u] = (d.patch ? g.patch : g.field)[d.off + x + (int64_t)y * d.sy + (int64_t)z * d.sz];
-        const int lx = x - (rx - 1) * NB, ly = y - (ry - 1) * NB, lz = z - (rz - 1) * NB;
-        const int bits = (lx < FL) | ((ly < FL) << 1) | ((lz < FL) << 2) | ((lx >= BL) << 3) |
-                         ((ly >= BL) << 4) | ((lz >= BL) << 5) |
-                         (((x & 1) | ((y & 1) << 1) | ((z & 1) << 2)) << 6);
+        const int x = (ex & 255) - 64, y = (ey & 255) - 64, z = (ez & 255) - 64;
+        v[u] = (d.patch ? g.patch : g.field)[d.off + (int64_t)(x + y * d.sy + z * d.sz)];
+        const int bits = ((ex >> 10) & 1) | (((ey >> 10) & 1) << 1) | (((ez >> 10) & 1) << 2) |
+                         (((ex >> 11) & 1) << 3) | (((ey >> 11) & 1) << 4) |
+                         (((ez >> 11) & 1) << 5) | (((ex >> 12) & 1) << 6) |
+                         (((ey >> 12) & 1) << 7) | (((ez >> 12) & 1) << 8);
         fl[u] = uint8_t((tab[r][bits >> 6] >> (bits & 63)) & 1);
         q.advance();
       }
@@ -647,17 +659,17 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
   __syncthreads();
   // degree 1: odd along one axis, the N even neighbours along it
   for_box(ax.nO, ay.nE, az.nE, [&](int i, int j, int k) {
-    const int row = (k * L1 + j) * L0;
+    const int row = imad24(imad24(k, L1, j), L0, 0);
     const int p = row + ax.nE + i;
     if (FLG[p]) V[p] = -gtaps<T, N>(V + row + i, 1);
   });
   for_box(ax.nE, ay.nO, az.nE, [&](int i, int j, int k) {
-    const int p = (k * L1 + ay.nE + j) * L0 + i;
-    if (FLG[p]) V[p] = -gtaps<T, N>(V + (k * L1 + j) * L0 + i, L0);
+    const int p = imad24(imad24(k, L1, ay.nE + j), L0, i);
+    if (FLG[p]) V[p] = -gtaps<T, N>(V + imad24(imad24(k, L1, j), L0, i), L0);
   });
   for_box(ax.nE, ay.nE, az.nO, [&](int i, int j, int k) {
-    const int p = ((az.nE + k) * L1 + j) * L0 + i;
-    if (FLG[p]) V[p] = -gtaps<T, N>(V + (k * L1 + j) * L0 + i, L01);
+    const int p = imad24(imad24(az.nE + k, L1, j), L0, i);
+    if (FLG[p]) V[p] = -gtaps<T, N>(V + imad24(imad24(k, L1, j), L0, i), L01);
   });
   __syncthreads();
   // degree 2: the tensor sum along the second odd axis into a temporary,
@@ -666,37 +678,38 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
   T* Txz = Txy + az.nE * ay.nO * L0;              // [nO_z][nE_y][L0]
   T* Tyz = Txz + az.nO * ay.nE * L0;              // [nO_z][L1][nE_x]
   for_box(L0, ay.nO, az.nE, [&](int c, int j, int k) {
-    T v = gtaps<T, N>(V + (k * L1 + j) * L0 + c, L0);
-    if (c < ax.nE) v += V[(k * L1 + ay.nE + j) * L0 + c];
-    Txy[(k * ay.nO + j) * L0 + c] = v;
+    T v = gtaps<T, N>(V + imad24(imad24(k, L1, j), L0, c), L0);
+    if (c < ax.nE) v += V[imad24(imad24(k, L1, ay.nE + j), L0, c)];
+    Txy[imad24(imad24(k, ay.nO, j), L0, c)] = v;
   });
   for_box(L0, ay.nE, az.nO, [&](int c, int j, int k) {
-    T v = gtaps<T, N>(V + (k * L1 + j) * L0 + c, L01);
-    if (c < ax.nE) v += V[((az.nE + k) * L1 + j) * L0 + c];
-    Txz[(k * ay.nE + j) * L0 + c] = v;
+    T v = gtaps<T, N>(V + imad24(imad24(k, L1, j), L0, c), L01);
+    if (c < ax.nE) v += V[imad24(imad24(az.nE + k, L1, j), L0, c)];
+    Txz[imad24(imad24(k, ay.nE, j), L0, c)] = v;
   });
   for_box(ax.nE, L1, az.nO, [&](int i, int c, int k) {
-    T v = gtaps<T, N>(V + (k * L1 + c) * L0 + i, L01);
-    if (c < ay.nE) v += V[((az.nE + k) * L1 + c) * L0 + i];
-    Tyz[(k * L1 + c) * ax.nE + i] = v;
+    T v = gtaps<T, N>(V + imad24(imad24(k, L1, c), L0, i), L01);
+    if (c < ay.nE) v += V[imad24(imad24(az.nE + k, L1, c), L0, i)];
+    Tyz[imad24(imad24(k, L1, c), ax.nE, i)] = v;
   });
   __syncthreads();
   // degree 2: then along the first odd axis (the temporary's odd entry holds
   // the other taps of the point's own column)
   for_box(ax.nO, ay.nO, az.nE, [&](int i, int j, int k) {
-    const int p = (k * L1 + ay.nE + j) * L0 + ax.nE + i;
-    const T* t = Txy + (k * ay.nO + j) * L0;
+    const int p = imad24(imad24(k, L1, ay.nE + j), L0, ax.nE + i);
+    const T* t = Txy + imad24(imad24(k, ay.nO, j), L0, 0);
     if (FLG[p]) V[p] = -(t[ax.nE + i] + gtaps<T, N>(t + i, 1));
   });
   for_box(ax.nO, ay.nE, az.nO, [&](int i, int j, int k) {
-    const int p = ((az.nE + k) * L1 + j) * L0 + ax.nE + i;
-    const T* t = Txz + (k * ay.nE + j) * L0;
+    const int p = imad24(imad24(az.nE + k, L1, j), L0, ax.nE + i);
+    const T* t = Txz + imad24(imad24(k, ay.nE, j), L0, 0);
     if (FLG[p]) V[p] = -(t[ax.nE + i] + gtaps<T, N>(t + i, 1));
   });
   for_box(ax.nE, ay.nO, az.nO, [&](int i, int j, int k) {
-    const int p = ((az.nE + k) * L1 + ay.nE + j) * L0 + i;
-    const T* t = Tyz + k * L1 * ax.nE + i;
-    if (FLG[p]) V[p] = -(t[(ay.nE + j) * ax.nE] + gtaps<T, N>(t + j * ax.nE, ax.nE));
+    const int p = imad24(imad24(az.nE + k, L1, ay.nE + j), L0, i);
+    const T* t = Tyz + imad24(imad24(k, L1, 0), ax.nE, i);
+    if (FLG[p])
+      V[p] = -(t[imad24(ay.nE + j, ax.nE, 0)] + gtaps<T, N>(t + imad24(j, ax.nE, 0), ax.nE));
   });
   __syncthreads();
   // degree 3: z, then y, then x; the central term is left out of the z sum
@@ -704,19 +717,21 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
   T* A = TMP;                                     // [nO_z][L1][L0]
   T* B = A + az.nO * L01;                         // [nO_z][nO_y][L0]
   for_box(L0, L1, az.nO, [&](int cx, int cy, int k) {
-    T v = gtaps<T, N>(V + (k * L1 + cy) * L0 + cx, L01);
-    if (cx < ax.nE || cy < ay.nE) v += V[((az.nE + k) * L1 + cy) * L0 + cx];
-    A[(k * L1 + cy) * L0 + cx] = v;
+    const int a = imad24(imad24(k, L1, cy), L0, cx);
+    T v = gtaps<T, N>(V + a, L01);
+    if (cx < ax.nE || cy < ay.nE) v += V[imad24(az.nE, L01, a)];
+    A[a] = v;
   });
   __syncthreads();
   for_box(L0, ay.nO, az.nO, [&](int c, int j, int k) {
-    const T* a = A + k * L01 + c;
-    B[(k * ay.nO + j) * L0 + c] = a[(ay.nE + j) * L0] + gtaps<T, N>(a + j * L0, L0);
+    const T* a = A + imad24(k, L01, c);
+    B[imad24(imad24(k, ay.nO, j), L0, c)] =
+        a[imad24(ay.nE + j, L0, 0)] + gtaps<T, N>(a + imad24(j, L0, 0), L0);
   });
   __syncthreads();
   for_box(ax.nO, ay.nO, az.nO, [&](int i, int j, int k) {
-    const int p = ((az.nE + k) * L1 + ay.nE + j) * L0 + ax.nE + i;
-    const T* b = B + (k * ay.nO + j) * L0;
+    const int p = imad24(imad24(az.nE + k, L1, ay.nE + j), L0, ax.nE + i);
+    const T* b = B + imad24(imad24(k, ay.nO, j), L0, 0);
     if (FLG[p]) V[p] = -(b[ax.nE + i] + gtaps<T, N>(b + i, 1));
   });
   __syncthreads();
@@ -729,7 +744,7 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
     const int cx = (x & 1) ? ax.nE + ((x - ax.o0) >> 1) : (x - ax.e0) >> 1;
     const int cy = (y & 1) ? ay.nE + ((y - ay.o0) >> 1) : (y - ay.e0) >> 1;
     const int cz = (z & 1) ? az.nE + ((z - az.o0) >> 1) : (z - az.e0) >> 1;
-    const int p = (cz * L1 + cy) * L0 + cx;
+    const int p = imad24(imad24(cz, L1, cy), L0, cx);
     if (FLG[p]) fb[(z * NB + y) * NB + x] = V[p];
   });
 }
