@@ -44,11 +44,27 @@ FINER, SAME, COARSER = 1, 0, -1
 
 def fd_weights(order):
     """Central first-derivative weights {offset: w} (times 1/h)."""
+    if order == 2:
+        return {-1: -0.5, 1: 0.5}
     if order == 4:
         return {-2: 1.0 / 12, -1: -8.0 / 12, 1: 8.0 / 12, 2: -1.0 / 12}
     if order == 6:
         return {-3: -1.0 / 60, -2: 9.0 / 60, -1: -45.0 / 60,
                 1: 45.0 / 60, 2: -9.0 / 60, 3: 1.0 / 60}
+    raise ValueError(order)
+
+
+def d2_weights(order):
+    """Central second-derivative weights {offset: w} (times 1/h^2) of order
+    2, 4 and 6: the DIFF-2 / DIFF-4 Laplacian stencils of the
+    finite-difference supplement and their sixth-order sibling."""
+    if order == 2:
+        return {-1: 1.0, 0: -2.0, 1: 1.0}
+    if order == 4:
+        return {-2: -1.0 / 12, -1: 16.0 / 12, 0: -30.0 / 12, 1: 16.0 / 12, 2: -1.0 / 12}
+    if order == 6:
+        return {-3: 2.0 / 180, -2: -27.0 / 180, -1: 270.0 / 180, 0: -490.0 / 180,
+                1: 270.0 / 180, 2: -27.0 / 180, 3: 2.0 / 180}
     raise ValueError(order)
 
 
@@ -91,9 +107,9 @@ def cons_fluxes(order, exact=False):
 
 
 def stencil_depth(order):
-    """Ghost points a block's RHS reads: FD4 and CONS-3 two, FD6 and CONS-5
-    three."""
-    return {3: 2, 4: 2, 5: 3, 6: 3}[order]
+    """Ghost points a block's RHS reads: FD2 one, FD4 and CONS-3 two, FD6
+    and CONS-5 three."""
+    return {2: 1, 3: 2, 4: 2, 5: 3, 6: 3}[order]
 
 
 def transform_reach(N, Nt):
@@ -467,7 +483,10 @@ class Grid:
         of that order, equal to -div(u phi) for the velocity fields used
         here, where each u_d does not depend on x_d.  fd_order 3 / 5: the
         conservative CONS-3 / CONS-5 form of the finite-difference
-        supplement (see cons_rhs_block)."""
+        supplement (see cons_rhs_block).  Velocity kind "diffusion" (nu,):
+        nu * laplacian(phi) (see diffusion_rhs_block)."""
+        if vel[0] == "diffusion":
+            return self.diffusion_rhs_block(key, vel[1][0])
         if self.fd_order in (3, 5):
             return self.cons_rhs_block(key, vel)
         g = self.fd_order // 2
@@ -481,6 +500,23 @@ class Grid:
         dz = sum(w[o] * Xg[g + o:g + o + nb, core, core] for o in sorted(w)) / h
         ux, uy, uz = self.velocity(vel, *self.positions(key))
         return -(ux * dx + uy * dy + uz * dz)
+
+    def diffusion_rhs_block(self, key, nu):
+        """Diffusion right-hand side nu * laplacian(phi) with the central
+        second differences of order fd_order (2: DIFF-2, 4: DIFF-4, 6) of
+        the finite-difference supplement, on the ghost-filled block."""
+        if self.fd_order not in (2, 4, 6):
+            raise ValueError("diffusion takes fd_order 2, 4 or 6")
+        g = self.fd_order // 2
+        Xg = self.ghost_block(key, g)
+        nb = self.nb
+        h = 1.0 / (nb << key[0])
+        w = d2_weights(self.fd_order)
+        core = slice(g, g + nb)
+        dxx = sum(w[o] * Xg[core, core, g + o:g + o + nb] for o in sorted(w))
+        dyy = sum(w[o] * Xg[core, g + o:g + o + nb, core] for o in sorted(w))
+        dzz = sum(w[o] * Xg[g + o:g + o + nb, core, core] for o in sorted(w))
+        return nu * (dxx + dyy + dzz) / (h * h)
 
     def cons_rhs_block(self, key, vel):
         """Conservative RHS of the finite-difference supplement:
