@@ -66,8 +66,9 @@ typedef struct {
                           (else MR_EINVAL at creation)                      */
   int32_t wavelet_N;   /* interpolation order N: 2, 4 or 6                  */
   int32_t wavelet_Nt;  /* vanishing moments Nt: 0 (Donoho) or 2 (lifted)    */
-  int32_t fd_order;    /* right-hand side: 4 or 6 = central finite
-                          differences of that order on -(u . grad) phi;
+  int32_t fd_order;    /* right-hand side: 2, 4 or 6 = central finite
+                          differences of that order on -(u . grad) phi
+                          (or on the Laplacian, MR_VEL_DIFFUSION);
                           3 or 5 = the conservative CONS-3 / CONS-5
                           fixed-weight WENO fluxes of the finite-difference
                           supplement (f^+ / f^- by the velocity's sign)     */
@@ -90,7 +91,14 @@ typedef struct {
  * so the advective and conservative forms coincide. */
 enum { MR_VEL_CONST = 0,    /* u = (p0, p1, p2)                             */
        MR_VEL_ROTATING = 1, /* u = (-(y - p1), x - p0, p2)                  */
-       MR_VEL_SHEAR = 2 };  /* u = (sin 2pi z, sin 2pi x, sin 2pi y)        */
+       MR_VEL_SHEAR = 2,    /* u = (sin 2pi z, sin 2pi x, sin 2pi y)        */
+       MR_VEL_DIFFUSION = 3 /* not a velocity: the right-hand side is
+                               p0 * laplacian(phi) with central second
+                               differences of order fd_order (2 = DIFF-2,
+                               4 = DIFF-4, 6) of the finite-difference
+                               supplement; fd_order 3 / 5 give MR_EINVAL;
+                               mr_cfl_dt gives cfl h^2 / (6 p0)            */
+};
 typedef struct {
   int32_t kind;
   int32_t reserved;
@@ -177,8 +185,8 @@ mr_status mr_init_ic(mr_grid* g, int32_t field, const mr_ic* ic, int32_t max_ite
  * block next to a coarser leaf, degree 1, 2 then 3 over the whole level
  * (section 2.3), written into the field; the patches of every coarse block
  * inside its finer regions (restriction of the substituted finer data).
- * Patches are `depth` points deep (0 = the stencil depth: 2 for
- * fd_order 3 and 4, 3 for 5 and 6).
+ * Patches are `depth` points deep (0 = the stencil depth: 1 for fd_order
+ * 2, 2 for 3 and 4, 3 for 5 and 6).
  * Asynchronous. */
 mr_status mr_ghost(mr_grid* g, int32_t field, int32_t depth);
 

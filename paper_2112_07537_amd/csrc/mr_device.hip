@@ -911,11 +911,24 @@ __global__ __launch_bounds__(256) void k_restrict(DevGrid<T> g, const RItem* __r
 }
 
 template <int FD> struct FDW;
+// central schemes: d/dx ~ sum_k c(k) (f[+k] - f[-k]) / h and, for the
+// diffusion operator (DIFF-2 / DIFF-4 of the finite-difference supplement,
+// and order 6), d2/dx2 ~ (d2(0) f[0] + sum_k d2(k) (f[+k] + f[-k])) / h^2
+template <> struct FDW<2> {
+  static constexpr int G = 1;
+  static constexpr bool CONS = false;
+  __device__ static constexpr double c(int) { return 0.5; }
+  __device__ static constexpr double d2(int k) { return k == 0 ? -2.0 : 1.0; }
+  __device__ static constexpr double cp(int) { return 0.0; }
+  __device__ static constexpr double cm(int) { return 0.0; }
+};
 template <> struct FDW<4> {
   static constexpr int G = 2;
   static constexpr bool CONS = false;
-  // d/dx ~ (c1 (f[+1]-f[-1]) + c2 (f[+2]-f[-2])) / h
   __device__ static constexpr double c(int k) { return k == 1 ? 8.0 / 12.0 : -1.0 / 12.0; }
+  __device__ static constexpr double d2(int k) {
+    return k == 0 ? -30.0 / 12.0 : (k == 1 ? 16.0 / 12.0 : -1.0 / 12.0);
+  }
   __device__ static constexpr double cp(int) { return 0.0; }
   __device__ static constexpr double cm(int) { return 0.0; }
 };
@@ -924,6 +937,10 @@ template <> struct FDW<6> {
   static constexpr bool CONS = false;
   __device__ static constexpr double c(int k) {
     return k == 1 ? 45.0 / 60.0 : (k == 2 ? -9.0 / 60.0 : 1.0 / 60.0);
+  }
+  __device__ static constexpr double d2(int k) {
+    return k == 0 ? -490.0 / 180.0
+                  : (k == 1 ? 270.0 / 180.0 : (k == 2 ? -27.0 / 180.0 : 2.0 / 180.0));
   }
   __device__ static constexpr double cp(int) { return 0.0; }
   __device__ static constexpr double cm(int) { return 0.0; }
@@ -943,6 +960,7 @@ template <> struct FDW<3> {
     return o == -2 ? 1.0 / 6.0 : o == -1 ? -1.0 : o == 0 ? 0.5 : o == 1 ? 1.0 / 3.0 : 0.0;
   }
   __device__ static constexpr double cm(int o) { return -cp(-o); }
+  __device__ static constexpr double d2(int) { return 0.0; }
 };
 template <> struct FDW<5> {
   static constexpr int G = 3;
@@ -953,6 +971,7 @@ template <> struct FDW<5> {
          : o == 0 ? 20.0 / 60.0 : o == 1 ? 30.0 / 60.0 : o == 2 ? -3.0 / 60.0 : 0.0;
   }
   __device__ static constexpr double cm(int o) { return -cp(-o); }
+  __device__ static constexpr double d2(int) { return 0.0; }
 };
 
 template <typename T, int FD, int NB>
@@ -1083,7 +1102,17 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
     __syncthreads();
     T dx = T(0), dy = T(0), dz = T(0);
     T dxm = T(0), dym = T(0), dzm = T(0);
-    if constexpr (!FDW<FD>::CONS) {
+    if (!FDW<FD>::CONS && vel.kind == 3) {
+      // diffusion: nu times the sum of the three second differences
+      const int c0 = (ty + G) * P + tx + G;
+      T lap = T(3.0 * FDW<FD>::d2(0)) * col[G];
+#pragma unroll
+      for (int kk = 1; kk <= G; ++kk)
+        lap += T(FDW<FD>::d2(kk)) * ((plane[c0 + kk] + plane[c0 - kk]) +
+                                     (plane[c0 + kk * P] + plane[c0 - kk * P]) +
+                                     (col[G + kk] + col[G - kk]));
+      dx = T(-vel.p[0] * inv_h) * lap;   // rhs = -(dx) * inv_h below
+    } else if constexpr (!FDW<FD>::CONS) {
 #pragma unroll
       for (int kk = 1; kk <= G; ++kk) {
         const T c = T(FDW<FD>::c(kk));
@@ -1113,7 +1142,10 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
       }
     }
     T ux, uy, uz;
-    if (vel.kind == 2) {
+    if (vel.kind == 3) {
+      ux = T(1);
+      uy = uz = T(0);
+    } else if (vel.kind == 2) {
       ux = vx_z[z];
       uy = vy_x[tx];
       uz = vz_y[ty];
@@ -1851,6 +1883,10 @@ static void rhs_t(const void* dgv, const void* un, void* out, int fd, double a, 
     if (g.nb == 8) rhs_nb<T, 4, 8>(g, un, out, a, b, c, dt, v, first, n, s);
     else if (g.nb == 16) rhs_nb<T, 4, 16>(g, un, out, a, b, c, dt, v, first, n, s);
     else rhs_nb<T, 4, 24>(g, un, out, a, b, c, dt, v, first, n, s);
+  } else if (fd == 2) {
+    if (g.nb == 8) rhs_nb<T, 2, 8>(g, un, out, a, b, c, dt, v, first, n, s);
+    else if (g.nb == 16) rhs_nb<T, 2, 16>(g, un, out, a, b, c, dt, v, first, n, s);
+    else rhs_nb<T, 2, 24>(g, un, out, a, b, c, dt, v, first, n, s);
   } else {
     if (g.nb == 8) rhs_nb<T, 6, 8>(g, un, out, a, b, c, dt, v, first, n, s);
     else if (g.nb == 16) rhs_nb<T, 6, 16>(g, un, out, a, b, c, dt, v, first, n, s);

@@ -1590,7 +1590,10 @@ static mr_status check_step_args(mr_grid* g, int32_t field, double dt, const mr_
                                  VelDev& vd) {
   if (!g || !vel || field < 0 || field >= g->cfg.n_fields) return fail(MR_EINVAL, "bad argument");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(MR_EINVAL, "dt must be positive");
-  if (vel->kind < 0 || vel->kind > 2) return fail(MR_EINVAL, "unknown velocity kind");
+  if (vel->kind < 0 || vel->kind > 3) return fail(MR_EINVAL, "unknown velocity kind");
+  if (vel->kind == MR_VEL_DIFFUSION &&
+      (g->cfg.fd_order % 2 != 0 || !(vel->p[0] >= 0) || !std::isfinite(vel->p[0])))
+    return fail(MR_EINVAL, "diffusion needs fd_order 2, 4 or 6 and a finite nu >= 0");
   vd = VelDev{};
   vd.kind = vel->kind;
   for (int i = 0; i < 8; ++i) vd.p[i] = vel->p[i];
@@ -1682,8 +1685,8 @@ mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, void* dev_pool,
   if (c.nb != 8 && c.nb != 16 && c.nb != 24) return fail(MR_EINVAL, "nb must be 8, 16 or 24");
   if (c.wavelet_N != 2 && c.wavelet_N != 4 && c.wavelet_N != 6) return fail(MR_EINVAL, "wavelet_N must be 2, 4 or 6");
   if (c.wavelet_Nt != 0 && c.wavelet_Nt != 2) return fail(MR_EINVAL, "wavelet_Nt must be 0 or 2");
-  if (c.fd_order < 3 || c.fd_order > 6)
-    return fail(MR_EINVAL, "fd_order must be 4 or 6 (central) or 3 or 5 (CONS-3 / CONS-5)");
+  if (c.fd_order < 2 || c.fd_order > 6)
+    return fail(MR_EINVAL, "fd_order must be 2, 4 or 6 (central) or 3 or 5 (CONS-3 / CONS-5)");
   if (c.level_min < 0 || c.level_max < c.level_min || c.level_max > 12)
     return fail(MR_EINVAL, "need 0 <= level_min <= level_max <= 12");
   if (c.prec != MR_F64 && c.prec != MR_F32) return fail(MR_EINVAL, "prec must be MR_F64 or MR_F32");
@@ -1726,7 +1729,7 @@ mr_status mr_grid_create(const mr_config* cfg, void* hip_stream, void* dev_pool,
   g->nb = c.nb;
   g->N = c.wavelet_N;
   g->Nt = c.wavelet_Nt;
-  g->G = (c.fd_order + 1) / 2;   // FD4 / CONS-3: 2, FD6 / CONS-5: 3
+  g->G = (c.fd_order + 1) / 2;   // FD2: 1, FD4 / CONS-3: 2, FD6 / CONS-5: 3
   const int H = Hreach(g->N, g->Nt);
   const int tf = std::max(H, g->N - 2), tb = std::max(H - 1, g->N - 1);
   g->Dw = std::max({g->G, tf, tb, g->N / 2, H});
@@ -2055,6 +2058,11 @@ mr_status mr_cfl_dt(const mr_grid* g, const mr_velocity* vel, double cfl, double
   int Lf = 0;
   for (const Key& k : g->leaves) Lf = std::max(Lf, k.L);
   const double h = 1.0 / double(g->nb << Lf);
+  if (vel->kind == MR_VEL_DIFFUSION) {
+    if (!(vel->p[0] > 0)) return fail(MR_EINVAL, "diffusion dt needs nu > 0");
+    *dt = cfl * h * h / (6.0 * vel->p[0]);   // explicit diffusion: h^2 / (2 d nu)
+    return MR_OK;
+  }
   *dt = cfl * h / usum(*vel);
   return MR_OK;
 }

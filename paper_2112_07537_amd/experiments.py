@@ -11,8 +11,9 @@
   represented field).
 * Two-level convergence (section 4.3): a uniform level with one eighth of
   the domain coarsened one level (jumps across faces, edges and corners),
-  ghost reconstruction, then the right-hand side on the whole grid against
-  the analytic operator applied to the Gaussian.
+  ghost reconstruction, then the right-hand side (advection CONS-3 / CONS-5
+  or central FD, or the DIFF-2 / DIFF-4 Laplacian) on the whole grid
+  against the analytic operator applied to the Gaussian.
 
 Geometry: the paper's domain is the cube [0, 2]^3 made of eight trees, the
 Gaussian exp(-r^2 / sigma^2) with sigma = 2/15 at its centre, N_b = 24 and
@@ -23,12 +24,13 @@ scaled by 1/2 (sigma = 1/15, the finest level 6; the Gaussian is below
 units: E_inf is scale free; moments scale by the volume (M_0 by 8) and one
 more factor 2 for M_1; derivatives d/dx of the paper are half of those
 here, so the advection velocity (1, 1, 1) of the paper is (1/2, 1/2, 1/2)
-here and h_f is twice the unit-cube spacing.
+here, the unit Laplacian of the paper is nu = 1/4 here, and h_f is twice
+the unit-cube spacing.
 
 Command line (JSON lines on stdout, one per run)::
 
     python -m paper_2112_07537_amd.experiments epsilon --wavelets 4.2 --lmax 6
-    python -m paper_2112_07537_amd.experiments twolevel --wavelets 4.2 --fd 3
+    python -m paper_2112_07537_amd.experiments twolevel --wavelets 4.2 --fd 3 --diff 2,4
     python -m paper_2112_07537_amd.experiments report RESULTS.jsonl FIGURES.txt
 """
 import argparse
@@ -137,9 +139,31 @@ def advection_exact(meta, nb, u, sigma=SIGMA, centre=CENTRE, chunk=1024):
         yield b0, (2.0 / sigma ** 2) * (u[0] * X + u[1] * Y + u[2] * Z) * f
 
 
-def two_level(wavelet, fd, levels=(2, 3, 4, 5), nb=24, u=(0.5, 0.5, 0.5), log=None):
+def laplacian_exact(meta, nb, nu, sigma=SIGMA, centre=CENTRE, chunk=1024):
+    """nu * laplacian(f) of the Gaussian at every point of the leaves, per
+    block (generator of (block range, values))."""
+    idx = np.arange(nb, dtype=np.float64)
+    for b0 in range(0, len(meta), chunk):
+        m = meta[b0:b0 + chunk]
+        den = (nb * (1 << m[:, 0].astype(np.int64))).astype(np.float64)
+        d = []
+        for a, c in zip((1, 2, 3), centre):
+            t = (m[:, a:a + 1] * nb + idx[None, :]) / den[:, None] - c
+            d.append(t - np.round(t))
+        X = d[0][:, None, None, :]
+        Y = d[1][:, None, :, None]
+        Z = d[2][:, :, None, None]
+        r2 = X * X + Y * Y + Z * Z
+        f = np.exp(-r2 / sigma ** 2)
+        yield b0, nu * (4.0 * r2 / sigma ** 4 - 6.0 / sigma ** 2) * f
+
+
+def two_level(wavelet, fd, levels=(2, 3, 4, 5), nb=24, u=(0.5, 0.5, 0.5), log=None,
+              diffusion=False):
     """Two-level convergence for one wavelet and scheme (fd_order 3 / 5:
-    CONS-3 / CONS-5; 4 / 6: central FD).  Yields one record per fine level."""
+    CONS-3 / CONS-5; 4 / 6: central FD advection; with diffusion=True,
+    fd_order 2 / 4: DIFF-2 / DIFF-4, nu = 1/4, the paper's unit Laplacian).
+    Yields one record per fine level."""
     N, Nt = parse_wavelet(wavelet)
     kind, par = gauss_ic()
     for L in levels:
@@ -152,13 +176,16 @@ def two_level(wavelet, fd, levels=(2, 3, 4, 5), nb=24, u=(0.5, 0.5, 0.5), log=No
             st = g.adapt_flags(two_level_tree_flags(g.block_meta(), L))
             if st.coarsened != 8 ** (L - 1) // 8:
                 raise RuntimeError("octant coarsening: %d sibling sets" % st.coarsened)
-            g.rhs(0, 1, mr.velocity("const", *u))
+            nu = 0.25
+            g.rhs(0, 1, mr.velocity("diffusion", nu) if diffusion else mr.velocity("const", *u))
             meta = g.block_meta()
             out = g.field_get(1)
             einf = 0.0
-            for b0, ref in advection_exact(meta, nb, u):
+            exact = laplacian_exact(meta, nb, nu) if diffusion else advection_exact(meta, nb, u)
+            for b0, ref in exact:
                 einf = max(einf, float(np.abs(out[b0:b0 + len(ref)] - ref).max()))
             rec = dict(experiment="twolevel", wavelet=wavelet, fd=fd, level=L, nb=nb,
+                       op="diff" if diffusion else "adv",
                        h_f=2.0 / (nb << L), n_blocks=int(len(meta)), e_inf=einf,
                        seconds=time.perf_counter() - t0)
         finally:
@@ -207,10 +234,13 @@ def report(results, figures):
         lines += ["## Two-level convergence (section 4.3)", "",
                   "| scheme | wavelet | h_f (paper units) | blocks | E_inf | paper E_inf | order |"
                   " paper order |", "|---|---|---|---|---|---|---|---|"]
-        name = {3: "cons3", 5: "cons5", 4: "fd4", 6: "fd6"}
-        for key in sorted({(r["fd"], r["wavelet"]) for r in tl}):
-            rows = sorted([r for r in tl if (r["fd"], r["wavelet"]) == key], key=lambda r: r["level"])
-            paper = sorted(set(fig.get(("e3_" + name[key[0]], key[1]), [])), reverse=True)
+        def name(r):
+            if r.get("op") == "diff":
+                return "diff%d" % r["fd"]
+            return {3: "cons3", 5: "cons5", 4: "fd4", 6: "fd6"}[r["fd"]]
+        for key in sorted({(name(r), r["wavelet"]) for r in tl}):
+            rows = sorted([r for r in tl if (name(r), r["wavelet"]) == key], key=lambda r: r["level"])
+            paper = sorted(set(fig.get(("e3_" + key[0], key[1]), [])), reverse=True)
             prev = pprev = None
             for i, r in enumerate(rows):
                 pe = [y for x, y in paper if abs(x - r["h_f"]) <= 1e-6 * r["h_f"]]
@@ -218,7 +248,7 @@ def report(results, figures):
                 order = math.log2(prev / r["e_inf"]) if prev else None
                 porder = math.log2(pprev / pe) if (pprev and pe) else None
                 lines.append("| %s | %s | %.6f | %d | %.3e | %s | %s | %s |" % (
-                    name[key[0]], key[1], r["h_f"], r["n_blocks"], r["e_inf"],
+                    key[0], key[1], r["h_f"], r["n_blocks"], r["e_inf"],
                     "%.3e" % pe if pe else "-", "%.2f" % order if order else "-",
                     "%.2f" % porder if porder else "-"))
                 prev, pprev = r["e_inf"], pe
@@ -236,6 +266,7 @@ def main(argv=None):
     b = sub.add_parser("twolevel")
     b.add_argument("--wavelets", default=",".join(WAVELETS))
     b.add_argument("--fd", default="3,5")
+    b.add_argument("--diff", default="", help="DIFF orders, e.g. 2,4")
     b.add_argument("--levels", default="2,3,4,5")
     c = sub.add_parser("report")
     c.add_argument("results")
@@ -251,9 +282,13 @@ def main(argv=None):
                 pass
     elif args.cmd == "twolevel":
         lv = tuple(int(v) for v in args.levels.split(","))
-        for fd in (int(v) for v in args.fd.split(",")):
+        for fd in (int(v) for v in args.fd.split(",") if v):
             for w in args.wavelets.split(","):
                 for _ in two_level(w, fd, lv, log=emit):
+                    pass
+        for fd in (int(v) for v in args.diff.split(",") if v):
+            for w in args.wavelets.split(","):
+                for _ in two_level(w, fd, lv, log=emit, diffusion=True):
                     pass
     else:
         print(report(args.results, args.figures))

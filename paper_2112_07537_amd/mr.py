@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libmr.so")
 
 MR_OK, MR_EINVAL, MR_ENOMEM, MR_ECAPACITY, MR_EHIP, MR_ESTATE, MR_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 MR_F64, MR_F32 = 0, 1
-MR_VEL_CONST, MR_VEL_ROTATING, MR_VEL_SHEAR = 0, 1, 2
+MR_VEL_CONST, MR_VEL_ROTATING, MR_VEL_SHEAR, MR_VEL_DIFFUSION = 0, 1, 2, 3
 MR_IC_GAUSS_SUM, MR_IC_TANH_SHELL = 0, 1
 
 
@@ -129,7 +129,7 @@ def device_arch():
 def velocity(kind, *p):
     v = mr_velocity()
     v.kind = {"const": MR_VEL_CONST, "rotating": MR_VEL_ROTATING,
-              "shear": MR_VEL_SHEAR}.get(kind, kind)
+              "shear": MR_VEL_SHEAR, "diffusion": MR_VEL_DIFFUSION}.get(kind, kind)
     for i, x in enumerate(p):
         v.p[i] = float(x)
     return v

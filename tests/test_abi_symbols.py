@@ -51,7 +51,7 @@ def test_validation_errors_without_device(lib):
     lib.mr_grid_create.restype = C.c_int32
     lib.mr_last_error.restype = C.c_char_p
     h = C.c_void_p()
-    bad = [dict(nb=12), dict(wavelet_N=3), dict(wavelet_Nt=1), dict(fd_order=2),
+    bad = [dict(nb=12), dict(wavelet_N=3), dict(wavelet_Nt=1), dict(fd_order=1), dict(fd_order=7),
            dict(level_min=3, level_max=2), dict(prec=7), dict(n_fields=0), dict(exec_mode=5)]
     for over in bad:
         kw = dict(nb=16, wavelet_N=4, wavelet_Nt=2, fd_order=4, level_min=0, level_max=4, prec=0,

@@ -11,7 +11,8 @@ caller-flag adaptation they use, on the GPU.
   compressed field refined back) to round-off.
 * Two-level convergence (section 4.3) on fine levels 2..4: the observed
   order approaches p = min(k, N - 1) for the advection schemes (k = 3 for
-  CONS-3, 5 for CONS-5).
+  CONS-3, 5 for CONS-5) and p = min(k, N - 2) for the DIFF-2 / DIFF-4
+  Laplacian.
 """
 import math
 
@@ -82,11 +83,15 @@ def test_epsilon_and_moments_small(w):
             assert r["m1"] <= 1e-13 * r["m0_value"], r
 
 
-@pytest.mark.parametrize("w,fd", [("2.2", 3), ("4.2", 3), ("4.0", 5), ("6.2", 5)])
-def test_two_level_convergence_small(w, fd):
+@pytest.mark.parametrize("w,fd,diff", [("2.2", 3, False), ("4.2", 3, False), ("4.0", 5, False),
+                                       ("6.2", 5, False), ("4.2", 2, True), ("6.2", 4, True),
+                                       ("4.0", 4, True)])
+def test_two_level_convergence_small(w, fd, diff):
+    """Advection: p = min(k, N - 1); the DIFF-2 / DIFF-4 Laplacian: p =
+    min(k, N - 2) (section 4.3)."""
     N = int(w[0])
-    p = min(fd, N - 1)
-    recs = list(ex.two_level(w, fd, levels=(2, 3, 4)))
+    p = min(fd, N - (2 if diff else 1))
+    recs = list(ex.two_level(w, fd, levels=(2, 3, 4), diffusion=diff))
     e = [r["e_inf"] for r in recs]
     orders = [math.log2(e[i] / e[i + 1]) for i in range(len(e) - 1)]
     print(w, fd, e, orders)
