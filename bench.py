@@ -321,6 +321,8 @@ def main():
     ap.add_argument("--config", default="c5")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-adapt", action="store_true",
+                    help="skip the adaptation leg (every other leg runs on the benchmark tree)")
     ap.add_argument("--breakdown-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 2 GiB device copy (counter calibration)")
@@ -404,7 +406,7 @@ def main():
             (cpu["value"], cpu["all_cores"] and "%.4g" % cpu["all_cores"]["value"]))
 
     # -- adaptation amortised (third loop, same grid, changes the tree)
-    if cfg.get("adapt_every"):
+    if cfg.get("adapt_every") and not args.no_adapt:
         g.prof_enable(False)   # clears the host phase timers
         ta_t, ta_pts, t_adapt, n_adapt = step_loop(g, cfg, max(args.steps, cfg["adapt_every"]),
                                                    adapt_every=cfg["adapt_every"])
