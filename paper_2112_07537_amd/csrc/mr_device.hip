@@ -233,17 +233,28 @@ __device__ __forceinline__ int64_t cell_index(const CellTab& ct, int L, int Ox, 
 // Flattened iteration over a 3D box [0,w0) x [0,w1) x [0,w2) with a fixed
 // thread stride, carrying the coordinates incrementally (no divisions in the
 // loop; the stride is decomposed once).
+// floor(a / b) for 0 <= a < 2^20 and 1 <= b < 2^11 through the FP32
+// reciprocal: (a + 1/2) / b lies at least 1/(2b) away from an integer, and
+// the relative error of the product (one rounding of a + 1/2, the
+// reciprocal's 1 ulp, one rounding of the product) stays below 2^-21, i.e.
+// below 1/(2b) in absolute terms for a below 2^20.
+__device__ __forceinline__ int div_small(int a, int b) {
+  return int((float(a) + 0.5f) * __builtin_amdgcn_rcpf(float(b)));
+}
+
 struct Iter3 {
   int x, y, z, w0, w1, sx, sy, sz;
+  // start, step < 2^20 (thread index and workgroup size); w0, w1 >= 1 and
+  // below 2^11 (box extents)
   __device__ __forceinline__ Iter3(int start, int step, int w0_, int w1_) : w0(w0_), w1(w1_) {
-    x = start % w0;
-    int t = start / w0;
-    y = t % w1;
-    z = t / w1;
-    sx = step % w0;
-    t = step / w0;
-    sy = t % w1;
-    sz = t / w1;
+    int t = div_small(start, w0);
+    x = start - t * w0;
+    z = div_small(t, w1);
+    y = t - z * w1;
+    t = div_small(step, w0);
+    sx = step - t * w0;
+    sz = div_small(t, w1);
+    sy = t - sz * w1;
   }
   __device__ __forceinline__ void advance() {
     x += sx;
@@ -581,13 +592,21 @@ __device__ __forceinline__ int imad24(int a, int b, int c) { return int(__umul24
 template <typename T, int N, int NT, int NB, int TPB>
 __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __restrict__ items) {
   extern __shared__ unsigned char lds_raw[];
-  __shared__ Desc desc[27];
-  __shared__ uint64_t tab[27][8];   // slab tables of the blocks owning the
+  // per region around F: byte address of the point (0, 0, 0) of F's frame in
+  // the buffer that holds the region, and the region's y and z strides
+  struct SDesc {
+    uint64_t base;
+    int32_t sy, sz;
+  };
+  __shared__ SDesc desc[27];
+  __shared__ uint32_t tab[27][16];  // slab tables of the blocks owning the
                                     // regions at F's level (zero otherwise)
-  // per axis and combined lattice index: coordinate relative to F (bits
-  // 0-7, +64), region (bits 8-9), the point's front / back slab membership
-  // and parity in the block holding it (bits 10-12: front, back, odd)
-  __shared__ int32_t lut[3][32];
+  // per axis and combined lattice index: .x the coordinate relative to F;
+  // .y the region's share of the region number (r = rx + 3 ry + 9 rz, bits
+  // 0-4) plus, from bit 8, the point's front / back slab membership and
+  // parity in the block holding it at bits a, 3 + a and 6 + a, so that the
+  // three axes' .y add up to the region and the slab-table bit index
+  __shared__ int2 lut[3][32];
   constexpr int R = N - 1;
   constexpr int FL = NT ? N : N - 1;        // front slab [0, FL)
   constexpr int BL = NT ? NB - N + 1 : NB - N + 2;   // back slab [BL, NB)
@@ -597,7 +616,14 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
   const SubstAxis ax = subst_axis(it.lo[0], it.hi[0], R);
   const SubstAxis ay = subst_axis(it.lo[1], it.hi[1], R);
   const SubstAxis az = subst_axis(it.lo[2], it.hi[2], R);
-  if (tid < 27) make_desc(g, F, tid, desc[tid]);
+  if (tid < 27) {
+    Desc d;
+    make_desc(g, F, tid, d);
+    const uint64_t buf = reinterpret_cast<uint64_t>(d.patch ? g.patch : g.field);
+    desc[tid].base = buf + uint64_t(d.off * (int64_t)sizeof(T));
+    desc[tid].sy = d.sy;
+    desc[tid].sz = d.sz;
+  }
   if (tid < 27 * 8) {
     const int r = tid >> 3, w = tid & 7;
     const int rx = r % 3, ry = (r / 3) % 3, rz = r / 9;
@@ -606,7 +632,9 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
     const int cz = rz == 0 ? 0 : (rz == 1 ? 1 : 3);
     const int o = r == 13 ? F : g.cmap[F * 64 + (cz * 4 + cy) * 4 + cx];
     const bool same = r == 13 || g.poff[(int64_t)F * 27 + r] < 0;
-    tab[r][w] = same ? g.stab[(int64_t)o * 8 + w] : 0ull;
+    const uint64_t t = same ? g.stab[(int64_t)o * 8 + w] : 0ull;
+    tab[r][2 * w] = uint32_t(t);
+    tab[r][2 * w + 1] = uint32_t(t >> 32);
   }
   if (tid < 96) {
     const int a = tid >> 5, c = tid & 31;
@@ -615,7 +643,8 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
       const int v = c < s.nE ? s.e0 + 2 * c : s.o0 + 2 * (c - s.nE);
       const int rg = v < 0 ? 0 : (v < NB ? 1 : 2);
       const int l = v - (rg - 1) * NB;
-      lut[a][c] = (v + 64) | (rg << 8) | (int(l < FL) << 10) | (int(l >= BL) << 11) | ((v & 1) << 12);
+      const int bits = (int(l < FL) << a) | (int(l >= BL) << (3 + a)) | ((v & 1) << (6 + a));
+      lut[a][c] = make_int2(v, rg * (a == 0 ? 1 : (a == 1 ? 3 : 9)) + (bits << 8));
     }
   }
   const int L0 = ax.nL, L1 = ay.nL;
@@ -635,17 +664,15 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
       uint8_t fl[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const bool in = i0 + u * nt < nV;
-        const int ex = lut[0][in ? q.x : 0], ey = lut[1][in ? q.y : 0], ez = lut[2][in ? q.z : 0];
-        const int r = ((ex >> 8) & 3) + 3 * ((ey >> 8) & 3) + 9 * ((ez >> 8) & 3);
-        const Desc d = desc[r];
-        const int x = (ex & 255) - 64, y = (ey & 255) - 64, z = (ez & 255) - 64;
-        v[u] = (d.patch ? g.patch : g.field)[d.off + (int64_t)(x + y * d.sy + z * d.sz)];
-        const int bits = ((ex >> 10) & 1) | (((ey >> 10) & 1) << 1) | (((ez >> 10) & 1) << 2) |
-                         (((ex >> 11) & 1) << 3) | (((ey >> 11) & 1) << 4) |
-                         (((ez >> 11) & 1) << 5) | (((ex >> 12) & 1) << 6) |
-                         (((ey >> 12) & 1) << 7) | (((ez >> 12) & 1) << 8);
-        fl[u] = uint8_t((tab[r][bits >> 6] >> (bits & 63)) & 1);
+        if (i0 + u * nt < nV) {
+          const int2 ex = lut[0][q.x], ey = lut[1][q.y], ez = lut[2][q.z];
+          const int sum = ex.y + ey.y + ez.y;
+          const int r = sum & 31, bits = sum >> 8;
+          const SDesc d = desc[r];
+          const int e = ex.x + __mul24(ey.x, d.sy) + __mul24(ez.x, d.sz);
+          v[u] = *reinterpret_cast<const T*>(d.base + uint64_t((int64_t)e * (int64_t)sizeof(T)));
+          fl[u] = uint8_t((tab[r][bits >> 5] >> (bits & 31)) & 1u);
+        }
         q.advance();
       }
 #pragma unroll
