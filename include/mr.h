@@ -138,7 +138,7 @@ typedef struct {
 typedef struct {
   int32_t lds_refine;     /* c->f items, default 20480                       */
   int32_t lds_restrict;   /* f->c items, default 24576                       */
-  int32_t lds_subst;      /* substitution items, default 61440               */
+  int32_t lds_subst;      /* substitution items, default 37888               */
   int32_t subst_threads;  /* 256 or 512, default 512                         */
   int32_t reserved[4];
 } mr_tuning;

@@ -26,12 +26,14 @@ from . import workloads as wl
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 
 CANDIDATES = {
-    "lds_subst": [24576, 32768, 40960, 49152, 55296, 61440],
+    # substitution budgets at the workgroup counts per CU that 160 KiB of LDS
+    # allows (6, 5, 4, 3 and 2 with the kernel's static tables), plus 61440
+    "lds_subst": [24320, 29696, 37888, 51200, 61440, 65536],
     "lds_refine": [12288, 16384, 20480, 24576, 32768],
     "lds_restrict": [16384, 20480, 24576, 32768, 40960],
     "subst_threads": [256, 512],
 }
-DEFAULTS = {"lds_refine": 20480, "lds_restrict": 24576, "lds_subst": 61440, "subst_threads": 512}
+DEFAULTS = {"lds_refine": 20480, "lds_restrict": 24576, "lds_subst": 37888, "subst_threads": 512}
 
 
 def gpu_arch():

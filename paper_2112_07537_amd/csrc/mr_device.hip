@@ -592,10 +592,13 @@ __device__ __forceinline__ int imad24(int a, int b, int c) { return int(__umul24
 template <typename T, int N, int NT, int NB, int TPB>
 __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __restrict__ items) {
   extern __shared__ unsigned char lds_raw[];
-  // per region around F: byte address of the point (0, 0, 0) of F's frame in
-  // the buffer that holds the region, and the region's y and z strides
+  // per region around F: element offset, from the start of the field, of
+  // the point (0, 0, 0) of F's frame in the buffer that holds the region
+  // (the field or the patch buffer: both are slices of one allocation or
+  // separate allocations aligned to the element size), and the region's y
+  // and z strides
   struct SDesc {
-    uint64_t base;
+    int64_t off;
     int32_t sy, sz;
   };
   __shared__ SDesc desc[27];
@@ -619,8 +622,10 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
   if (tid < 27) {
     Desc d;
     make_desc(g, F, tid, d);
-    const uint64_t buf = reinterpret_cast<uint64_t>(d.patch ? g.patch : g.field);
-    desc[tid].base = buf + uint64_t(d.off * (int64_t)sizeof(T));
+    const int64_t pshift =
+        (int64_t)(reinterpret_cast<uintptr_t>(g.patch) - reinterpret_cast<uintptr_t>(g.field)) /
+        (int64_t)sizeof(T);
+    desc[tid].off = d.off + (d.patch ? pshift : 0);
     desc[tid].sy = d.sy;
     desc[tid].sz = d.sz;
   }
@@ -650,37 +655,49 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
   const int L0 = ax.nL, L1 = ay.nL;
   const int L01 = L0 * L1;
   const int nV = L01 * az.nL;
+  // LDS: the lattice values, their slab flags as a bit mask (64 lattice
+  // points a word), then the temporaries of the tensor sums
   T* V = reinterpret_cast<T*>(lds_raw);
-  uint8_t* FLG = reinterpret_cast<uint8_t*>(V + nV);
-  T* TMP = reinterpret_cast<T*>(lds_raw + ((size_t(nV) * (sizeof(T) + 1) + sizeof(T) - 1) /
-                                           sizeof(T)) * sizeof(T));
+  const int vbytes = (nV * int(sizeof(T)) + 7) & ~7;
+  uint64_t* FLW = reinterpret_cast<uint64_t*>(lds_raw + vbytes);
+  const uint32_t* FL32 = reinterpret_cast<const uint32_t*>(FLW);
+  T* TMP = reinterpret_cast<T*>(lds_raw + vbytes + ((nV + 63) >> 6) * 8);
+  auto flag = [&](int p) { return (FL32[p >> 5] >> (p & 31)) & 1u; };
   __syncthreads();
   {
     // stage the lattice, value and slab flag; U loads in flight per thread
+    // (lanes past the lattice's end work on its point 0 and store nothing)
     constexpr int U = 8;
+    const T* fld = g.field;
     Iter3 q(tid, nt, L0, L1);
     for (int i0 = tid; i0 < nV; i0 += U * nt) {
       T v[U];
-      uint8_t fl[U];
+      uint32_t fl[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
+        fl[u] = 0u;
         if (i0 + u * nt < nV) {
           const int2 ex = lut[0][q.x], ey = lut[1][q.y], ez = lut[2][q.z];
           const int sum = ex.y + ey.y + ez.y;
           const int r = sum & 31, bits = sum >> 8;
           const SDesc d = desc[r];
           const int e = ex.x + __mul24(ey.x, d.sy) + __mul24(ez.x, d.sz);
-          v[u] = *reinterpret_cast<const T*>(d.base + uint64_t((int64_t)e * (int64_t)sizeof(T)));
-          fl[u] = uint8_t((tab[r][bits >> 5] >> (bits & 31)) & 1u);
+          v[u] = fld[d.off + e];
+          fl[u] = (tab[r][bits >> 5] >> (bits & 31)) & 1u;
         }
         q.advance();
       }
+      // the 64 lanes of a wave hold 64 consecutive lattice points from a
+      // multiple of 64 on; lane 0, the wave's first, writes their flag word
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (i0 + u * nt < nV) {
-          V[i0 + u * nt] = v[u];
-          FLG[i0 + u * nt] = fl[u];
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * nt;
+        const uint64_t m = __ballot(i < nV && fl[u] != 0u);
+        if (i < nV) {
+          V[i] = v[u];
+          if ((tid & 63) == 0) FLW[i >> 6] = m;
         }
+      }
     }
   }
   __syncthreads();
@@ -688,59 +705,69 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
   for_box(ax.nO, ay.nE, az.nE, [&](int i, int j, int k) {
     const int row = imad24(imad24(k, L1, j), L0, 0);
     const int p = row + ax.nE + i;
-    if (FLG[p]) V[p] = -gtaps<T, N>(V + row + i, 1);
+    if (flag(p)) V[p] = -gtaps<T, N>(V + row + i, 1);
   });
   for_box(ax.nE, ay.nO, az.nE, [&](int i, int j, int k) {
     const int p = imad24(imad24(k, L1, ay.nE + j), L0, i);
-    if (FLG[p]) V[p] = -gtaps<T, N>(V + imad24(imad24(k, L1, j), L0, i), L0);
+    if (flag(p)) V[p] = -gtaps<T, N>(V + imad24(imad24(k, L1, j), L0, i), L0);
   });
   for_box(ax.nE, ay.nE, az.nO, [&](int i, int j, int k) {
     const int p = imad24(imad24(az.nE + k, L1, j), L0, i);
-    if (FLG[p]) V[p] = -gtaps<T, N>(V + imad24(imad24(k, L1, j), L0, i), L01);
+    if (flag(p)) V[p] = -gtaps<T, N>(V + imad24(imad24(k, L1, j), L0, i), L01);
   });
   __syncthreads();
   // degree 2: the tensor sum along the second odd axis into a temporary,
-  // without the central term where that would be the point itself
-  T* Txy = TMP;                                   // [nE_z][nO_y][L0]
-  T* Txz = Txy + az.nE * ay.nO * L0;              // [nO_z][nE_y][L0]
-  T* Tyz = Txz + az.nO * ay.nE * L0;              // [nO_z][L1][nE_x]
-  for_box(L0, ay.nO, az.nE, [&](int c, int j, int k) {
-    T v = gtaps<T, N>(V + imad24(imad24(k, L1, j), L0, c), L0);
-    if (c < ax.nE) v += V[imad24(imad24(k, L1, ay.nE + j), L0, c)];
-    Txy[imad24(imad24(k, ay.nO, j), L0, c)] = v;
-  });
-  for_box(L0, ay.nE, az.nO, [&](int c, int j, int k) {
-    T v = gtaps<T, N>(V + imad24(imad24(k, L1, j), L0, c), L01);
-    if (c < ax.nE) v += V[imad24(imad24(az.nE + k, L1, j), L0, c)];
-    Txz[imad24(imad24(k, ay.nE, j), L0, c)] = v;
-  });
-  for_box(ax.nE, L1, az.nO, [&](int i, int c, int k) {
-    T v = gtaps<T, N>(V + imad24(imad24(k, L1, c), L0, i), L01);
-    if (c < ay.nE) v += V[imad24(imad24(az.nE + k, L1, c), L0, i)];
-    Tyz[imad24(imad24(k, L1, c), ax.nE, i)] = v;
-  });
-  __syncthreads();
-  // degree 2: then along the first odd axis (the temporary's odd entry holds
-  // the other taps of the point's own column)
-  for_box(ax.nO, ay.nO, az.nE, [&](int i, int j, int k) {
-    const int p = imad24(imad24(k, L1, ay.nE + j), L0, ax.nE + i);
-    const T* t = Txy + imad24(imad24(k, ay.nO, j), L0, 0);
-    if (FLG[p]) V[p] = -(t[ax.nE + i] + gtaps<T, N>(t + i, 1));
-  });
-  for_box(ax.nO, ay.nE, az.nO, [&](int i, int j, int k) {
-    const int p = imad24(imad24(az.nE + k, L1, j), L0, ax.nE + i);
-    const T* t = Txz + imad24(imad24(k, ay.nE, j), L0, 0);
-    if (FLG[p]) V[p] = -(t[ax.nE + i] + gtaps<T, N>(t + i, 1));
-  });
-  for_box(ax.nE, ay.nO, az.nO, [&](int i, int j, int k) {
-    const int p = imad24(imad24(az.nE + k, L1, ay.nE + j), L0, i);
-    const T* t = Tyz + imad24(imad24(k, L1, 0), ax.nE, i);
-    if (FLG[p])
-      V[p] = -(t[imad24(ay.nE + j, ax.nE, 0)] + gtaps<T, N>(t + imad24(j, ax.nE, 0), ax.nE));
-  });
-  __syncthreads();
+  // without the central term where that would be the point itself, then
+  // along the first odd axis (the temporary's odd entry holds the other taps
+  // of the point's own column).  The (x, y) and (x, z) classes share one
+  // round and the (y, z) class reuses their temporaries' space; a degree-2
+  // point reads only points of degree 0 and 1, so the order of the classes
+  // does not matter.
+  {
+    T* Txy = TMP;                                 // [nE_z][nO_y][L0]
+    T* Txz = Txy + az.nE * ay.nO * L0;            // [nO_z][nE_y][L0]
+    for_box(L0, ay.nO, az.nE, [&](int c, int j, int k) {
+      T v = gtaps<T, N>(V + imad24(imad24(k, L1, j), L0, c), L0);
+      if (c < ax.nE) v += V[imad24(imad24(k, L1, ay.nE + j), L0, c)];
+      Txy[imad24(imad24(k, ay.nO, j), L0, c)] = v;
+    });
+    for_box(L0, ay.nE, az.nO, [&](int c, int j, int k) {
+      T v = gtaps<T, N>(V + imad24(imad24(k, L1, j), L0, c), L01);
+      if (c < ax.nE) v += V[imad24(imad24(az.nE + k, L1, j), L0, c)];
+      Txz[imad24(imad24(k, ay.nE, j), L0, c)] = v;
+    });
+    __syncthreads();
+    for_box(ax.nO, ay.nO, az.nE, [&](int i, int j, int k) {
+      const int p = imad24(imad24(k, L1, ay.nE + j), L0, ax.nE + i);
+      const T* t = Txy + imad24(imad24(k, ay.nO, j), L0, 0);
+      if (flag(p)) V[p] = -(t[ax.nE + i] + gtaps<T, N>(t + i, 1));
+    });
+    for_box(ax.nO, ay.nE, az.nO, [&](int i, int j, int k) {
+      const int p = imad24(imad24(az.nE + k, L1, j), L0, ax.nE + i);
+      const T* t = Txz + imad24(imad24(k, ay.nE, j), L0, 0);
+      if (flag(p)) V[p] = -(t[ax.nE + i] + gtaps<T, N>(t + i, 1));
+    });
+    __syncthreads();
+  }
+  if (az.nO > 0 && ay.nO > 0) {
+    T* Tyz = TMP;                                 // [nO_z][L1][nE_x]
+    for_box(ax.nE, L1, az.nO, [&](int i, int c, int k) {
+      T v = gtaps<T, N>(V + imad24(imad24(k, L1, c), L0, i), L01);
+      if (c < ay.nE) v += V[imad24(imad24(az.nE + k, L1, c), L0, i)];
+      Tyz[imad24(imad24(k, L1, c), ax.nE, i)] = v;
+    });
+    __syncthreads();
+    for_box(ax.nE, ay.nO, az.nO, [&](int i, int j, int k) {
+      const int p = imad24(imad24(az.nE + k, L1, ay.nE + j), L0, i);
+      const T* t = Tyz + imad24(imad24(k, L1, 0), ax.nE, i);
+      if (flag(p))
+        V[p] = -(t[imad24(ay.nE + j, ax.nE, 0)] + gtaps<T, N>(t + imad24(j, ax.nE, 0), ax.nE));
+    });
+    __syncthreads();
+  }
   // degree 3: z, then y, then x; the central term is left out of the z sum
   // at the odd-odd (x, y) columns, which only their own point reads
+  if (ax.nO > 0 && ay.nO > 0 && az.nO > 0) {
   T* A = TMP;                                     // [nO_z][L1][L0]
   T* B = A + az.nO * L01;                         // [nO_z][nO_y][L0]
   for_box(L0, L1, az.nO, [&](int cx, int cy, int k) {
@@ -759,9 +786,10 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
   for_box(ax.nO, ay.nO, az.nO, [&](int i, int j, int k) {
     const int p = imad24(imad24(az.nE + k, L1, ay.nE + j), L0, ax.nE + i);
     const T* b = B + imad24(imad24(k, ay.nO, j), L0, 0);
-    if (FLG[p]) V[p] = -(b[ax.nE + i] + gtaps<T, N>(b + i, 1));
+    if (flag(p)) V[p] = -(b[ax.nE + i] + gtaps<T, N>(b + i, 1));
   });
   __syncthreads();
+  }
   // the box's slab points to the field, in natural order
   T* fb = g.field + (int64_t)F * (NB * NB * NB);
   const int b0 = it.hi[0] - it.lo[0], b1 = it.hi[1] - it.lo[1], b2 = it.hi[2] - it.lo[2];
@@ -772,7 +800,7 @@ __global__ __launch_bounds__(TPB) void k_subst(DevGrid<T> g, const GItem* __rest
     const int cy = (y & 1) ? ay.nE + ((y - ay.o0) >> 1) : (y - ay.e0) >> 1;
     const int cz = (z & 1) ? az.nE + ((z - az.o0) >> 1) : (z - az.e0) >> 1;
     const int p = imad24(imad24(cz, L1, cy), L0, cx);
-    if (FLG[p]) fb[(z * NB + y) * NB + x] = V[p];
+    if (flag(p)) fb[(z * NB + y) * NB + x] = V[p];
   });
 }
 

@@ -183,7 +183,7 @@ using namespace mr;
 // an f->c sum follows its tile's thinnest axis.
 static const int kLdsBudgetRefine = 20 * 1024;
 static const int kLdsBudgetRestrict = 24 * 1024;
-static const int kLdsBudgetSubst = 60 * 1024;
+static const int kLdsBudgetSubst = 37 * 1024;
 static const int kSubstThreads = 512;
 
 struct mr_grid {
@@ -432,8 +432,9 @@ static int rview_lds(const RItem& it, int H, size_t esz) {
 
 // LDS of a substitution item (k_subst): the lattice of its box (per axis
 // the even coordinates within N-1 of the box and the odd ones inside it),
-// one value and one flag byte per point, then the larger of the degree-2
-// and degree-3 temporaries of the separable tensor sums.
+// one value per point padded to 8 bytes, one flag bit per point in 64-bit
+// words, then the larger of the degree-2 temporaries ((x, y) and (x, z)
+// classes together, or the (y, z) class) and the degree-3 ones.
 static int subst_lds(const GItem& it, int N, size_t esz) {
   const int R = N - 1;
   int nE[3], nO[3], nL[3];
@@ -445,10 +446,10 @@ static int subst_lds(const GItem& it, int N, size_t esz) {
     nL[a] = nE[a] + nO[a];
   }
   const size_t nV = size_t(nL[0]) * nL[1] * nL[2];
-  const size_t t2 = size_t(nE[2]) * nO[1] * nL[0] + size_t(nO[2]) * nE[1] * nL[0] +
-                    size_t(nO[2]) * nL[1] * nE[0];
+  const size_t t2 = std::max(size_t(nE[2]) * nO[1] * nL[0] + size_t(nO[2]) * nE[1] * nL[0],
+                             size_t(nO[2]) * nL[1] * nE[0]);
   const size_t t3 = size_t(nO[2]) * nL[1] * nL[0] + size_t(nO[2]) * nO[1] * nL[0];
-  const size_t head = (nV * (esz + 1) + esz - 1) / esz * esz;
+  const size_t head = ((nV * esz + 7) & ~size_t(7)) + (nV + 63) / 64 * 8;
   return int(head + std::max(t2, t3) * esz);
 }
 
