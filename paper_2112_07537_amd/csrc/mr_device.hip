@@ -1240,12 +1240,33 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
 
 // smallest v' >= v with v' = rem (mod m)
 constexpr int pad_to(int v, int m, int rem) { return v + ((rem - v % m) % m + m) % m; }
+
+// Smallest row stride >= v (in 4-byte words) for which 32 lanes reading
+// word r * stride + step * t (lane = r * per_row + t, t < per_row) hit 32
+// distinct LDS banks; v itself when no stride below v + 32 does.
+constexpr int bank_free_stride(int v, int per_row, int step) {
+  for (int s = v; s < v + 32; ++s) {
+    unsigned used = 0;
+    bool ok = true;
+    for (int l = 0; l < 32 && ok; ++l) {
+      const int b = ((l / per_row) * s + step * (l % per_row)) % 32;
+      ok = !((used >> b) & 1u);
+      used |= 1u << b;
+    }
+    if (ok) return s;
+  }
+  return v;
+}
 // ------------------------------------------------------------------ details
 // Forward transform (x, then y, then z) of the ghost-filled block in FP64,
 // per-block maxima of |gamma| over 27 (x-class, y-class, z-class) boxes:
 // class 0 = [0, nb), 1 = [0, eb), 2 = [nb-ef, nb).
 // Planes are taken ZG at a time: every barrier phase (staging, x pass,
-// y pass) works on the whole group, so a plane costs 3/ZG barriers.  With
+// y pass) works on the whole group, so a plane costs 3/ZG barriers.  The
+// input planes are staged in the field's precision (exact) and converted
+// when read; the x pass computes XP consecutive (H^a, G^a) pairs of a row
+// per thread and the y pass YP pairs of a column, so that a value read from
+// LDS serves several outputs.  With
 // 24^3 blocks one workgroup fills a CU whatever its LDS (registers limit
 // it), so the group is 4 planes; smaller blocks keep it at 2 so that LDS
 // does not cap the workgroups per CU.
@@ -1262,18 +1283,28 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
   constexpr int P = NB + HF + HB;
   constexpr int LPT = (P * P + NB * NB - 1) / (NB * NB);
   constexpr int NP = NB / 2;
+  constexpr int XP = NP % 3 == 0 ? 3 : (NP % 2 == 0 ? 2 : 1);   // pairs per x task
+  constexpr int YP = NP % 2 == 0 ? 2 : 1;                       // pairs per y task
+  constexpr int XT = NP / XP, YT = NP / YP;                    // tasks per row, column
+  // offsets (from the first pair's even point) of the values a task reads
+  constexpr int DLO = -(HR > GR - 1 ? HR : GR - 1);
+  constexpr int DHX = 2 * (XP - 1) + (HR > GR + 1 ? HR : GR + 1);
+  constexpr int DHY = 2 * (YP - 1) + (HR > GR + 1 ? HR : GR + 1);
   static_assert(PF >= ZG, "a group's planes are loaded before it starts");
   // LDS layout, chosen so that the lanes of one access fall on distinct
   // banks (32 banks of 4 bytes):
   // * a staged plane is split into its even and odd x columns (x counted
-  //   from the block origin), so the x pass reads consecutive doubles;
-  //   rows of PH = NP (mod 16) doubles continue each other's banks, and
-  //   the odd half starts 8 doubles (16 banks) after the even half;
+  //   from the block origin), so the x pass reads consecutive values; the
+  //   row stride PH puts the 32 lanes of a half-wave (rows of XT tasks,
+  //   XP values apart) on distinct banks (4-byte values), or continues the
+  //   banks of the previous row (8-byte values, PH = NP mod 16); the odd
+  //   half starts 16 banks after the even half;
   // * x-pass rows of NBS doubles, 2 NBS = NB (mod 16), for the y pass.
-  constexpr int PH = pad_to((P + 1) / 2, 16, NP % 16);
-  constexpr int PS = pad_to(P * PH, 16, 8);
+  constexpr int PH = sizeof(T) == 4 ? bank_free_stride((P + 1) / 2, XT, XP)
+                                    : pad_to((P + 1) / 2, 16, NP % 16);
+  constexpr int PS = sizeof(T) == 4 ? pad_to(P * PH, 32, 16) : pad_to(P * PH, 16, 8);
   constexpr int NBS = pad_to(NB, 8, (NB % 16) / 2);
-  __shared__ double pl[ZG][2 * PS];   // input planes in FP64: even, odd columns
+  __shared__ __align__(16) T pl[ZG][2 * PS];   // input planes: even, odd columns
   __shared__ double t1[ZG][P * NBS];  // after the x pass
   __shared__ double t2[ZG][NB * NB];  // after the y pass
   __shared__ Desc desc[27];
@@ -1351,7 +1382,7 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
 #pragma unroll
         for (int k = 0; k < LPT; ++k) {
           const int i = tid + k * NB * NB;
-          if (k < LPT - 1 || i < P * P) pl[q][sidx[k]] = double(cur[k]);
+          if (k < LPT - 1 || i < P * P) pl[q][sidx[k]] = cur[k];
         }
       }
     }
@@ -1365,45 +1396,56 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
       }
     }
     if (live) {
-      // x pass by pairs: H^a at the even point 2j, G^a at 2j+1 of each row,
-      // for every plane of the group
-      for (int i = tid; i < P * NP; i += NB * NB) {
-        const int j = i % NP, yy = i / NP;
+      // x pass: H^a at the even points 2j, G^a at 2j+1 of each row, for XP
+      // consecutive pairs j0 .. j0+XP-1 per thread, every plane of the group
+      for (int i = tid; i < ZG * P * XT; i += NB * NB) {
+        const int jt = i % XT, rq = i / XT;
+        const int q = rq / P, yy = rq % P;
+        if (z0 + q > ZLAST) continue;
+        const int j0 = jt * XP;
+        // the value at x = 2 j0 + d: even or odd half by the parity of d
+        const T* row = pl[q] + yy * PH + j0;
+        double w[DHX - DLO + 1];
 #pragma unroll
-        for (int q = 0; q < ZG; ++q) {
-          if (z0 + q > ZLAST) continue;
-          // the value at x = 2j + d: even or odd half by the parity of d
-          const double* row = pl[q] + yy * PH + j;
-          auto at = [&](int d) {
-            return (d & 1) ? row[PS + ((d + HF) >> 1)] : row[(d + HF) >> 1];
-          };
+        for (int d = DLO; d <= DHX; ++d)
+          w[d - DLO] = double((d & 1) ? row[PS + ((d + HF) >> 1)] : row[(d + HF) >> 1]);
+#pragma unroll
+        for (int p = 0; p < XP; ++p) {
           double ev = 0.0, od = 0.0;
 #pragma unroll
           for (int o = -HR; o <= HR; ++o)
-            if (Ha<N, NT>::c(o) != 0.0) ev += Ha<N, NT>::c(o) * at(o);
+            if (Ha<N, NT>::c(o) != 0.0) ev += Ha<N, NT>::c(o) * w[2 * p + o - DLO];
 #pragma unroll
           for (int o = -GR; o <= GR; ++o)
-            if (Ga<N>::c(o) != 0.0) od += Ga<N>::c(o) * at(1 + o);
-          t1[q][yy * NBS + 2 * j] = ev;
-          t1[q][yy * NBS + 2 * j + 1] = od;
+            if (Ga<N>::c(o) != 0.0) od += Ga<N>::c(o) * w[2 * p + 1 + o - DLO];
+          t1[q][yy * NBS + 2 * (j0 + p)] = ev;
+          t1[q][yy * NBS + 2 * (j0 + p) + 1] = od;
         }
       }
       __syncthreads();
-      // y pass by pairs: (plane, column x, rows 2j (H^a) and 2j+1 (G^a))
-      for (int i = tid; i < ZG * NB * NP; i += NB * NB) {
-        const int q = i / (NB * NP), r = i % (NB * NP);
-        const int x = r % NB, j = r / NB;
+      // y pass: (plane, column x, rows 2j (H^a) and 2j+1 (G^a)) for YP
+      // consecutive pairs per thread
+      for (int i = tid; i < ZG * NB * YT; i += NB * NB) {
+        const int x = i % NB, r = i / NB;
+        const int jt = r % YT, q = r / YT;
         if (z0 + q > ZLAST) continue;
-        const double* col = t1[q] + (2 * j + HF) * NBS + x;
-        double ev = 0.0, od = 0.0;
+        const int j0 = jt * YP;
+        const double* col = t1[q] + (2 * j0 + HF) * NBS + x;
+        double w[DHY - DLO + 1];
 #pragma unroll
-        for (int o = -HR; o <= HR; ++o)
-          if (Ha<N, NT>::c(o) != 0.0) ev += Ha<N, NT>::c(o) * col[o * NBS];
+        for (int d = DLO; d <= DHY; ++d) w[d - DLO] = col[d * NBS];
 #pragma unroll
-        for (int o = -GR; o <= GR; ++o)
-          if (Ga<N>::c(o) != 0.0) od += Ga<N>::c(o) * col[(1 + o) * NBS];
-        t2[q][2 * j * NB + x] = ev;
-        t2[q][(2 * j + 1) * NB + x] = od;
+        for (int p = 0; p < YP; ++p) {
+          double ev = 0.0, od = 0.0;
+#pragma unroll
+          for (int o = -HR; o <= HR; ++o)
+            if (Ha<N, NT>::c(o) != 0.0) ev += Ha<N, NT>::c(o) * w[2 * p + o - DLO];
+#pragma unroll
+          for (int o = -GR; o <= GR; ++o)
+            if (Ga<N>::c(o) != 0.0) od += Ga<N>::c(o) * w[2 * p + 1 + o - DLO];
+          t2[q][2 * (j0 + p) * NB + x] = ev;
+          t2[q][(2 * (j0 + p) + 1) * NB + x] = od;
+        }
       }
       __syncthreads();
     }
@@ -1445,9 +1487,15 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
   // their LDS reads are issued back to back.  (No LDS atomics: a contended
   // atomic max is expanded into a per-lane loop.)  The buffers of the plane
   // loop are free once every thread has passed the first barrier below.
-  double* colmax = &pl[0][0];          // [cz][ty][tx]
-  double* rowmax = &t1[0][0];          // [cz][ty][cx]
-  static_assert(ZG * 2 * PS >= 3 * NB * NB && ZG * P * NBS >= 9 * NB, "reduction buffers");
+  // (in the x-pass buffer, or the input planes', or a buffer of their own
+  // where neither holds them)
+  constexpr bool CM_T1 = ZG * P * NBS >= 3 * NB * NB;
+  constexpr bool CM_PL = !CM_T1 && ZG * 2 * PS * sizeof(T) >= 3 * NB * NB * sizeof(double);
+  __shared__ double cm_own[CM_T1 || CM_PL ? 1 : 3 * NB * NB];
+  double* colmax = CM_T1 ? &t1[0][0]
+                         : (CM_PL ? reinterpret_cast<double*>(&pl[0][0]) : cm_own);   // [cz][ty][tx]
+  double* rowmax = &t2[0][0];          // [cz][ty][cx]
+  static_assert(ZG * NB * NB >= 9 * NB, "reduction buffers");
   if (bad) nonfinite = 1;
   __syncthreads();
   colmax[tid] = m0;
