@@ -1241,6 +1241,19 @@ __global__ __launch_bounds__(NB* NB) void k_rhs(DevGrid<T> g, const T* __restric
 // smallest v' >= v with v' = rem (mod m)
 constexpr int pad_to(int v, int m, int rem) { return v + ((rem - v % m) % m + m) % m; }
 
+// Lifting form of the analysis pair: G^a at an odd point is the point minus
+// the DD prediction from the N even points around it; for Nt = 2, H^a at an
+// even point is the point plus a quarter of the two G^a values beside it
+// (the update that gives H^a its taps).  w is a window of values, i the odd
+// point's index in it.
+template <int N>
+__device__ __forceinline__ double lift_gamma(const double* w, int i) {
+  double g = w[i];
+#pragma unroll
+  for (int k = 0; k < N; ++k) g -= DD<N>::w(k) * w[i - 1 + 2 * (k + DD<N>::J0)];
+  return g;
+}
+
 // Smallest row stride >= v (in 4-byte words) for which 32 lanes reading
 // word r * stride + step * t (lane = r * per_row + t, t < per_row) hit 32
 // distinct LDS banks; v itself when no stride below v + 32 does.
@@ -1266,7 +1279,8 @@ constexpr int bank_free_stride(int v, int per_row, int step) {
 // input planes are staged in the field's precision (exact) and converted
 // when read; the x pass computes XP consecutive (H^a, G^a) pairs of a row
 // per thread and the y pass YP pairs of a column, so that a value read from
-// LDS serves several outputs.  With
+// LDS serves several outputs.  Every pass uses the lifting form of the
+// filters (lift_gamma), half the multiply-adds of the H^a / G^a taps.  With
 // 24^3 blocks one workgroup fills a CU whatever its LDS (registers limit
 // it), so the group is 4 planes; smaller blocks keep it at 2 so that LDS
 // does not cap the workgroups per CU.
@@ -1355,6 +1369,7 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
 #pragma unroll
   for (int i = 0; i < 2 * R + 1; ++i) ring[i] = 0.0;   // planes below -HF: no tap reaches them
   double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+  double gz = 0.0;   // G^a of the last odd plane computed ahead (Nt = 2)
   bool bad = false;
   // PF planes in flight (a register ring); the whole plane loop is unrolled,
   // so plane index, region changes, output parity and the ring rotations
@@ -1409,17 +1424,14 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
 #pragma unroll
         for (int d = DLO; d <= DHX; ++d)
           w[d - DLO] = double((d & 1) ? row[PS + ((d + HF) >> 1)] : row[(d + HF) >> 1]);
+        double gm[XP + 1];   // G^a at the odd points 2p - 1, p = 0 .. XP
+#pragma unroll
+        for (int p = NT ? 0 : 1; p <= XP; ++p) gm[p] = lift_gamma<N>(w, 2 * p - 1 - DLO);
 #pragma unroll
         for (int p = 0; p < XP; ++p) {
-          double ev = 0.0, od = 0.0;
-#pragma unroll
-          for (int o = -HR; o <= HR; ++o)
-            if (Ha<N, NT>::c(o) != 0.0) ev += Ha<N, NT>::c(o) * w[2 * p + o - DLO];
-#pragma unroll
-          for (int o = -GR; o <= GR; ++o)
-            if (Ga<N>::c(o) != 0.0) od += Ga<N>::c(o) * w[2 * p + 1 + o - DLO];
+          const double ev = NT ? w[2 * p - DLO] + 0.25 * (gm[p] + gm[p + 1]) : w[2 * p - DLO];
           t1[q][yy * NBS + 2 * (j0 + p)] = ev;
-          t1[q][yy * NBS + 2 * (j0 + p) + 1] = od;
+          t1[q][yy * NBS + 2 * (j0 + p) + 1] = gm[p + 1];
         }
       }
       __syncthreads();
@@ -1434,17 +1446,14 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
         double w[DHY - DLO + 1];
 #pragma unroll
         for (int d = DLO; d <= DHY; ++d) w[d - DLO] = col[d * NBS];
+        double gm[YP + 1];
+#pragma unroll
+        for (int p = NT ? 0 : 1; p <= YP; ++p) gm[p] = lift_gamma<N>(w, 2 * p - 1 - DLO);
 #pragma unroll
         for (int p = 0; p < YP; ++p) {
-          double ev = 0.0, od = 0.0;
-#pragma unroll
-          for (int o = -HR; o <= HR; ++o)
-            if (Ha<N, NT>::c(o) != 0.0) ev += Ha<N, NT>::c(o) * w[2 * p + o - DLO];
-#pragma unroll
-          for (int o = -GR; o <= GR; ++o)
-            if (Ga<N>::c(o) != 0.0) od += Ga<N>::c(o) * w[2 * p + 1 + o - DLO];
+          const double ev = NT ? w[2 * p - DLO] + 0.25 * (gm[p] + gm[p + 1]) : w[2 * p - DLO];
           t2[q][2 * (j0 + p) * NB + x] = ev;
-          t2[q][(2 * (j0 + p) + 1) * NB + x] = od;
+          t2[q][(2 * (j0 + p) + 1) * NB + x] = gm[p + 1];
         }
       }
       __syncthreads();
@@ -1459,15 +1468,21 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
       ring[2 * R] = v;
       const int zo = zi - R;
       if (zo >= 0 && zo < NB) {
-        double gsum = 0.0;
+        // ring[R + o] holds plane zo + o; with Nt = 2 the G^a value of the
+        // odd plane after an even output is computed with it and kept for
+        // that plane's own output (gz), as is the one before (gz, or the
+        // plane -1's at zo = 0)
+        double gsum;
         if ((zo & 1) == 0) {
-#pragma unroll
-          for (int o = -HR; o <= HR; ++o)
-            if (Ha<N, NT>::c(o) != 0.0) gsum += Ha<N, NT>::c(o) * ring[R + o];
+          if (NT) {
+            const double gp = zo == 0 ? lift_gamma<N>(ring, R - 1) : gz;
+            gz = lift_gamma<N>(ring, R + 1);
+            gsum = ring[R] + 0.25 * (gp + gz);
+          } else {
+            gsum = ring[R];
+          }
         } else {
-#pragma unroll
-          for (int o = -GR; o <= GR; ++o)
-            if (Ga<N>::c(o) != 0.0) gsum += Ga<N>::c(o) * ring[R + o];
+          gsum = NT ? gz : lift_gamma<N>(ring, R);
         }
         const bool isdet = (zo & 1) != 0 || ((tx | ty) & 1) != 0;
         const double a = isdet ? fabs(gsum) : 0.0;
