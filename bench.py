@@ -71,6 +71,7 @@ def step_loop(g, cfg, steps, adapt_every=0):
         g.rk3_step(dt, vel)
         g.details_async()
         if adapt_every and (s + 1) % adapt_every == 0:
+            g.sync()   # the queued steps are not adaptation time
             ta = time.perf_counter()
             g.adapt()
             t_adapt += time.perf_counter() - ta
