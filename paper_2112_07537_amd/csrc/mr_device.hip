@@ -136,15 +136,26 @@ __device__ __forceinline__ int wrapi(int a, int w) {
   return r < 0 ? r + w : r;
 }
 
+// floor(a / b) for 0 <= a < 2^20 and 1 <= b < 2^11 through the FP32
+// reciprocal: (a + 1/2) / b lies at least 1/(2b) away from an integer, and
+// the relative error of the product (one rounding of a + 1/2, the
+// reciprocal's 1 ulp, one rounding of the product) stays below 2^-21, i.e.
+// below 1/(2b) in absolute terms for a below 2^20.
+__device__ __forceinline__ int div_small(int a, int b) {
+  return int((float(a) + 0.5f) * __builtin_amdgcn_rcpf(float(b)));
+}
+
 // Leaf id holding the level-(L+up) point q given relative to block m.
 template <typename T>
 __device__ __forceinline__ int owner_id(const DevGrid<T>& g, int m, int up, int qx, int qy, int qz) {
   const int h = g.nb >> 1;
-  int cx = ((qx >> up) + h) / h, cy = ((qy >> up) + h) / h, cz = ((qz >> up) + h) / h;
-  if ((unsigned)cx > 3u || (unsigned)cy > 3u || (unsigned)cz > 3u) {
+  const int ax = (qx >> up) + h, ay = (qy >> up) + h, az = (qz >> up) + h;
+  if ((unsigned)ax >= unsigned(4 * h) || (unsigned)ay >= unsigned(4 * h) ||
+      (unsigned)az >= unsigned(4 * h)) {
     atomicAdd(g.err, 1);
     return -1;
   }
+  const int cx = div_small(ax, h), cy = div_small(ay, h), cz = div_small(az, h);
   return g.cmap[m * 64 + (cz * 4 + cy) * 4 + cx];
 }
 
@@ -233,15 +244,6 @@ __device__ __forceinline__ int64_t cell_index(const CellTab& ct, int L, int Ox, 
 // Flattened iteration over a 3D box [0,w0) x [0,w1) x [0,w2) with a fixed
 // thread stride, carrying the coordinates incrementally (no divisions in the
 // loop; the stride is decomposed once).
-// floor(a / b) for 0 <= a < 2^20 and 1 <= b < 2^11 through the FP32
-// reciprocal: (a + 1/2) / b lies at least 1/(2b) away from an integer, and
-// the relative error of the product (one rounding of a + 1/2, the
-// reciprocal's 1 ulp, one rounding of the product) stays below 2^-21, i.e.
-// below 1/(2b) in absolute terms for a below 2^20.
-__device__ __forceinline__ int div_small(int a, int b) {
-  return int((float(a) + 0.5f) * __builtin_amdgcn_rcpf(float(b)));
-}
-
 struct Iter3 {
   int x, y, z, w0, w1, sx, sy, sz;
   // start, step < 2^20 (thread index and workgroup size); w0, w1 >= 1 and
@@ -1582,35 +1584,11 @@ struct PassIO {
   double* dout;
   const double* det;
   const int32_t* det_slot;
-  const int32_t* det_dirs;  // per slot: kDiscardAll, or the directions of the
-                            // coarsening neighbours of a kept block
+  const uint32_t* det_tab;  // per slot: 16 words, bit (front | back << 3 |
+                            // parity << 6) set when the slot's details with
+                            // that per-axis slab membership are discarded
   T* dst;  // destination field array (new pool)
 };
-
-// Coarse-extension slab of a fine block toward the directions in `dirs`
-// (bit r = (dx+1) + 3 (dy+1) + 9 (dz+1)), whose details the update discards
-// with those of the coarsening neighbours (section 2.2.1, Table 3 coarse
-// region extension): every point with an odd index within [0, N) in front
-// and [nb-N+1, nb) behind along each facing axis (lifted), [0, N-1) and
-// [nb-N+2, nb) (N.0).
-template <int N, int NT>
-__device__ __forceinline__ bool in_extension(int nb, int x, int y, int z, int dirs) {
-  if (((x | y | z) & 1) == 0) return false;
-  const int p[3] = {x, y, z};
-  const int front = NT ? N : N - 1;
-  const int back = NT ? nb - N + 1 : nb - N + 2;
-  for (int r = 0; r < 27; ++r) {
-    if (r == 13 || !((dirs >> r) & 1)) continue;
-    const int d[3] = {r % 3 - 1, (r / 3) % 3 - 1, r / 9 - 1};
-    bool in = true;
-    for (int a = 0; a < 3; ++a) {
-      if (d[a] < 0) in = in && p[a] < front;
-      else if (d[a] > 0) in = in && p[a] >= back;
-    }
-    if (in) return true;
-  }
-  return false;
-}
 
 template <typename T, int N, int NT>
 __device__ __forceinline__ double pass_in(const DevGrid<T>& g, const PItem& it, int src_mode,
@@ -1626,7 +1604,11 @@ __device__ __forceinline__ double pass_in(const DevGrid<T>& g, const PItem& it, 
     return io.din[it.in_off + ((int64_t)iz * it.isz[1] + iy) * it.isz[0] + ix];
   }
   // src_mode 2: discarded details (old tree): every detail of a coarsening
-  // child, the coarse-extension slab of a kept same-level neighbour
+  // child; of a kept same-level neighbour, every point with an odd index in
+  // its coarse-extension slab toward the coarsening children (section 2.2.1,
+  // Table 3 coarse region extension: [0, N) in front and [nb-N+1, nb)
+  // behind along each facing axis for lifted wavelets, [0, N-1) and
+  // [nb-N+2, nb) for N.0), looked up in the slot's table
   const int id = owner_id(g, it.src_blk, 0, x, y, z);
   if (id < 0) return 0.0;
   const int s = io.det_slot[id];
@@ -1635,11 +1617,17 @@ __device__ __forceinline__ double pass_in(const DevGrid<T>& g, const PItem& it, 
   const int L = g.lev[it.src_blk];
   if (g.lev[id] != L) return 0.0;
   const int W = nb << L;
-  const int gx = wrapi(g.ijk[3 * it.src_blk] * nb + x, W) - g.ijk[3 * id] * nb;
-  const int gy = wrapi(g.ijk[3 * it.src_blk + 1] * nb + y, W) - g.ijk[3 * id + 1] * nb;
-  const int gz = wrapi(g.ijk[3 * it.src_blk + 2] * nb + z, W) - g.ijk[3 * id + 2] * nb;
-  const int dirs = io.det_dirs[s];
-  if (dirs != kDiscardAll && !in_extension<N, NT>(nb, gx, gy, gz, dirs)) return 0.0;
+  // the sample lies within one block of the source block, so one wrap fixes it
+  auto wrap1 = [W](int a) { return a < 0 ? a + W : (a >= W ? a - W : a); };
+  const int gx = wrap1(g.ijk[3 * it.src_blk] * nb + x) - g.ijk[3 * id] * nb;
+  const int gy = wrap1(g.ijk[3 * it.src_blk + 1] * nb + y) - g.ijk[3 * id + 1] * nb;
+  const int gz = wrap1(g.ijk[3 * it.src_blk + 2] * nb + z) - g.ijk[3 * id + 2] * nb;
+  constexpr int FRONT = NT ? N : N - 1;
+  const int back = NT ? nb - N + 1 : nb - N + 2;
+  const int bit = int(gx < FRONT) | (int(gy < FRONT) << 1) | (int(gz < FRONT) << 2) |
+                  (int(gx >= back) << 3) | (int(gy >= back) << 4) | (int(gz >= back) << 5) |
+                  ((gx & 1) << 6) | ((gy & 1) << 7) | ((gz & 1) << 8);
+  if (!((io.det_tab[(int64_t)s * 16 + (bit >> 5)] >> (bit & 31)) & 1u)) return 0.0;
   return io.det[(int64_t)s * nb * nb * nb + ((int64_t)gz * nb + gy) * nb + gx];
 }
 
@@ -2114,21 +2102,21 @@ void launch_fill(bool f32, void* dst, size_t n, hipStream_t s) {
 template <typename T>
 static void pass_t(const void* dgv, Wavelet w, int filter, int axis, int src_mode, int dst_mode,
                    const PItem* items, int n, const double* din, double* dout, const double* det,
-                   const int32_t* slot, const int32_t* dirs, void* dst, hipStream_t s) {
+                   const int32_t* slot, const uint32_t* tab, void* dst, hipStream_t s) {
   const DevGrid<T>& g = *static_cast<const DevGrid<T>*>(dgv);
-  PassIO<T> io{din, dout, det, slot, dirs, static_cast<T*>(dst)};
+  PassIO<T> io{din, dout, det, slot, tab, static_cast<T*>(dst)};
   MR_WAVELET_SWITCH(w, hipLaunchKernelGGL((k_pass<T, N_, NT_>), dim3(n), dim3(256), 0, s, g, items,
                                           filter, axis, src_mode, dst_mode, io));
 }
 void launch_pass(bool f32, const void* dgv, Wavelet w, int filter, int axis, int src_mode,
                  int dst_mode, const PItem* items, int n, const double* din, double* dout,
-                 const double* det, const int32_t* slot, const int32_t* dirs, void* dst,
+                 const double* det, const int32_t* slot, const uint32_t* tab, void* dst,
                  hipStream_t s) {
   if (n <= 0) return;
   if (f32)
-    pass_t<float>(dgv, w, filter, axis, src_mode, dst_mode, items, n, din, dout, det, slot, dirs, dst, s);
+    pass_t<float>(dgv, w, filter, axis, src_mode, dst_mode, items, n, din, dout, det, slot, tab, dst, s);
   else
-    pass_t<double>(dgv, w, filter, axis, src_mode, dst_mode, items, n, din, dout, det, slot, dirs, dst, s);
+    pass_t<double>(dgv, w, filter, axis, src_mode, dst_mode, items, n, din, dout, det, slot, tab, dst, s);
 }
 
 }  // namespace mr

@@ -775,6 +775,31 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
   return MR_OK;
 }
 
+// Per coarser region r around a block: bit (lo | hi << 3 | parity << 6) set
+// when a point whose per-axis front / back slab range membership is lo / hi
+// and whose index parities are `parity` (not all even) lies in the slab
+// toward r (front along axes where r lies below, back where above).
+static const std::array<std::array<uint64_t, 8>, 27>& slab_region_tables() {
+  static const std::array<std::array<uint64_t, 8>, 27> t = [] {
+    std::array<std::array<uint64_t, 8>, 27> t{};
+    for (int r = 0; r < 27; ++r) {
+      if (r == 13) continue;
+      const int d[3] = {r % 3 - 1, (r / 3) % 3 - 1, r / 9 - 1};
+      for (int idx = 0; idx < 512; ++idx) {
+        const int lo = idx & 7, hi = (idx >> 3) & 7, par = idx >> 6;
+        bool ok = par != 0;
+        for (int a = 0; a < 3; ++a) {
+          if (d[a] < 0 && !((lo >> a) & 1)) ok = false;
+          if (d[a] > 0 && !((hi >> a) & 1)) ok = false;
+        }
+        if (ok) t[r][idx >> 6] |= 1ull << (idx & 63);
+      }
+    }
+    return t;
+  }();
+  return t;
+}
+
 // Upload tree metadata and rebuild every derived structure.
 static mr_status commit_tree_impl(mr_grid* g);
 static void build_cell_tables(mr_grid* g);
@@ -831,36 +856,18 @@ static mr_status commit_tree_impl(mr_grid* g) {
   // slab tables (READING R-SUB): bit (lo | hi << 3 | parity << 6) of a block
   // is set when a point whose per-axis front / back slab range membership is
   // lo / hi and whose index parities are `parity` lies in one of the slabs
-  // of the block's coarser regions and passes that slab's selector; built
-  // once per distinct mask
+  // of the block's coarser regions and passes that slab's selector (every
+  // detail of the slab, both families); a block's table is the union of the
+  // tables of its coarser regions, each built once
   {
-    std::unordered_map<int32_t, std::array<uint64_t, 8>> memo;
-    auto table = [&](int32_t m) {
-      std::array<uint64_t, 8> t{};
-      for (int idx = 0; idx < 512; ++idx) {
-        const int lo = idx & 7, hi = (idx >> 3) & 7, par = idx >> 6;
-        bool in = false;
-        for (int r = 0; r < 27 && !in; ++r) {
-          if (r == 13 || !((m >> r) & 1)) continue;
-          const int d[3] = {r % 3 - 1, (r / 3) % 3 - 1, r / 9 - 1};
-          bool ok = true;
-          for (int a = 0; a < 3; ++a) {
-            if (d[a] < 0 && !((lo >> a) & 1)) ok = false;
-            if (d[a] > 0 && !((hi >> a) & 1)) ok = false;
-          }
-          in = ok && par != 0;   // every detail of the slab, both families
-        }
-        if (in) t[idx >> 6] |= 1ull << (idx & 63);
-      }
-      return t;
-    };
-    for (int b = 0; b < n; ++b)
-      if (!memo.count(cdir[b])) memo.emplace(cdir[b], table(cdir[b]));
+    const auto& region_table = slab_region_tables();
     g->stab_host.assign(size_t(n) * 8, 0);
     parallel_for(size_t(n), [&](size_t lo_b, size_t hi_b) {
       for (size_t b = lo_b; b < hi_b; ++b) {
-        const auto& t = memo.at(cdir[b]);
-        for (int w = 0; w < 8; ++w) g->stab_host[b * 8 + w] = t[w];
+        const int32_t m = cdir[b];
+        for (int r = 0; r < 27; ++r)
+          if ((m >> r) & 1)
+            for (int w = 0; w < 8; ++w) g->stab_host[b * 8 + w] |= region_table[r][w];
       }
     });
   }
@@ -888,10 +895,21 @@ static mr_status commit_tree_impl(mr_grid* g) {
     HIPCHK(g->d_cstep.ensure(64 * size_t(n) * sizeof(int32_t)));
     build_cell_tables(g);
   }
+  // the stage-depth and wide work lists are independent: build them on two
+  // threads (the error message of the other thread is carried over)
+  mr_status st_w = MR_OK;
+  std::string msg_w;
+  std::thread tw([&] {
+    st_w = build_lists(g, g->Dw, g->wide);
+    if (st_w != MR_OK) msg_w = g_errmsg;
+  });
   st = build_lists(g, g->G, g->stage);
+  tw.join();
   if (st != MR_OK) return st;
-  st = build_lists(g, g->Dw, g->wide);
-  if (st != MR_OK) return st;
+  if (st_w != MR_OK) {
+    g_errmsg = msg_w;
+    return st_w;
+  }
   HIPCHK(hipStreamSynchronize(g->stream));  // host vectors above are staged
   ++g->tree_version;
   return MR_OK;
@@ -1349,10 +1367,27 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
     DevBuf& d_scr = g->ad_scr;
     DevBuf& d_det = g->ad_det;
     DevBuf& d_slot = g->ad_slot;
+    // per slot the table of discarded details: all details of a coarsening
+    // child, the union of the slabs toward its directions for a kept block
     DevBuf& d_dirs = g->ad_dirs;
-    HIPCHK(d_dirs.ensure(std::max(1, nslot) * sizeof(int32_t)));
+    std::vector<uint64_t> dtab(size_t(std::max(1, nslot)) * 8, 0);
+    {
+      const auto& rt = slab_region_tables();
+      for (int sl = 0; sl < nslot; ++sl) {
+        uint64_t* t = &dtab[size_t(sl) * 8];
+        if (dirs[sl] == kDiscardAll) {
+          for (int w = 1; w < 8; ++w) t[w] = ~0ull;   // every point with an odd index
+        } else {
+          for (int r = 0; r < 27; ++r)
+            if ((dirs[sl] >> r) & 1)
+              for (int w = 0; w < 8; ++w) t[w] |= rt[r][w];
+        }
+      }
+    }
+    HIPCHK(d_dirs.ensure(dtab.size() * sizeof(uint64_t)));
     if (nslot)
-      HIPCHK(hipMemcpyAsync(d_dirs.p, dirs.data(), nslot * sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
+      HIPCHK(hipMemcpyAsync(d_dirs.p, dtab.data(), size_t(nslot) * 8 * sizeof(uint64_t),
+                            hipMemcpyHostToDevice, g->stream));
     HIPCHK(d_scr.ensure(std::max<int64_t>(1, scr) * sizeof(double)));
     HIPCHK(d_det.ensure(std::max<int64_t>(1, int64_t(nslot) * nb * nb * nb) * sizeof(double)));
     HIPCHK(d_slot.ensure(std::max(1, n_old) * sizeof(int32_t)));
@@ -1397,7 +1432,7 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
       for (int p = 0; p < 3; ++p)
         launch_pass(g->f32, v.raw, w, F_SYNTH, ax[p], p == 0 ? 2 : 1, p == 2 ? 2 : 0, items + offs[6 + p],
                     int(upd[p].size()), scrp, scrp, static_cast<const double*>(d_det.p),
-                    static_cast<const int32_t*>(d_slot.p), static_cast<const int32_t*>(d_dirs.p),
+                    static_cast<const int32_t*>(d_slot.p), static_cast<const uint32_t*>(d_dirs.p),
                     dst, g->stream);
     }
     mr_status st = check_err(g);

@@ -128,15 +128,18 @@ void launch_copy_blocks(bool f32, const void* src, void* dst, const int32_t* pai
                         int nb, hipStream_t s);
 void launch_fill(bool f32, void* dst, size_t n, hipStream_t s);
 // src_mode: 0 gather the ext field of src_blk, 1 FP64 scratch box (din),
-// 2 discarded details (det, det_slot per old block); dst_mode: 0 FP64 scratch
-// box (dout), 1 store into dst field block, 2 subtract from dst field block
-// (block-local coordinates = output - dlo).
+// 2 discarded details (det, det_slot per old block, det_tab: per slot 16
+// words of 32 bits, bit (front | back << 3 | parity << 6) set when the
+// slot's details with that per-axis slab membership and parity are
+// discarded); dst_mode: 0 FP64 scratch box (dout), 1 store into dst field
+// block, 2 subtract from dst field block (block-local coordinates = output -
+// dlo).
 void launch_pass(bool f32, const void* dg, Wavelet w, int filter, int axis, int src_mode,
                  int dst_mode, const PItem* items, int n_items, const double* din, double* dout,
-                 const double* det, const int32_t* det_slot, const int32_t* det_dirs, void* dst,
+                 const double* det, const int32_t* det_slot, const uint32_t* det_tab, void* dst,
                  hipStream_t s);
 
-// det_dirs value of a coarsening child: all its details are discarded.
+// Direction mask of a coarsening child's slot: all its details are discarded.
 constexpr int32_t kDiscardAll = 1 << 27;
 // Device address (current device) of the static band-maxima scratch of
 // mr_details_noalloc, resolved once per device; its capacity in blocks.

@@ -34,8 +34,8 @@ def run(g):
     return st.n_blocks, g.block_meta().copy(), g.field_get().copy(), nrm
 
 
-def test_caller_pool_matches_library_allocation():
-    import torch
+def test_caller_pool_matches_library_allocation(torch_cuda):
+    torch = torch_cuda
     need = mr.pool_bytes(**KW)
     pool = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
     base = pool.data_ptr()
