@@ -359,19 +359,23 @@ __global__ __launch_bounds__(256) void k_gview(DevGrid<T> g, const GItem* __rest
   T* T2 = S;
   __syncthreads();
   {
-    constexpr int U = 16;   // one round of loads covers a side item's samples
+    // one round of loads covers a side item's samples; slots past the end
+    // skip their work (whole waves at a time)
+    constexpr int U = 16;
     const int n = cs[0] * cs[1] * cs[2];
+    const int lin0 = clo[0] + NB * clo[1] + NB * NB * clo[2];
     Iter3 q(tid, nt, cs[0], cs[1]);
     for (int i0 = tid; i0 < n; i0 += U * nt) {
       T v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const bool in = i0 + u * nt < n;
-        const int qx = in ? q.x : 0, qy = in ? q.y : 0, qz = in ? q.z : 0;
-        const int k = (acell[2][qz] * 4 + acell[1][qy]) * 4 + acell[0][qx];
-        const int64_t idx = cbase[k] + (int64_t)cstep[k] * ((clo[0] + qx) + NB * (clo[1] + qy) +
-                                                            NB * NB * (clo[2] + qz));
-        v[u] = g.field[idx];
+        if (i0 + u * nt < n) {
+          const int k = (acell[2][q.z] * 4 + acell[1][q.y]) * 4 + acell[0][q.x];
+          // sample offset from the cell's base: step times the F-frame
+          // linear index (|index| < 2^23, step <= 4)
+          const int lin = lin0 + q.x + NB * q.y + NB * NB * q.z;
+          v[u] = g.field[cbase[k] + __mul24(cstep[k], lin)];
+        }
         q.advance();
       }
 #pragma unroll
