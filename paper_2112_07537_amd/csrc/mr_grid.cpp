@@ -1147,26 +1147,41 @@ static void plan_from_flags(mr_grid* g, const std::vector<int>& flag,
       if (created.count(pack(k.L, k.i, k.j, k.k))) continue;
       groups[pack(k.L - 1, k.i >> 1, k.j >> 1, k.k >> 1)]++;
     }
-    for (auto& kv : groups) {
-      if (kv.second != 8) continue;
-      const int Lp = int(kv.first >> 60);
-      const int pi = int((kv.first >> 40) & 0xFFFFF), pj = int((kv.first >> 20) & 0xFFFFF),
-                pk = int(kv.first & 0xFFFFF);
-      bool ok = true;
-      for (int c = 0; c < 8 && ok; ++c) {
-        const int b = find_leaf(g, Lp + 1, 2 * pi + (c & 1), 2 * pj + ((c >> 1) & 1), 2 * pk + ((c >> 2) & 1));
-        for (int dz = -1; dz <= 1 && ok; ++dz)
-          for (int dy = -1; dy <= 1 && ok; ++dy)
-            for (int dx = -1; dx <= 1 && ok; ++dx) {
-              if (!dx && !dy && !dz) continue;
-              int id;
-              const int kind = neighbor_kind(g, b, dx, dy, dz, &id);
-              if (kind == 1) ok = false;                       // finer neighbour
-              else if (kind == 0 && plan.refine[id]) ok = false;  // refining neighbour
-            }
+    // complete sibling sets, checked for finer or refining neighbours on
+    // host threads (the parents keep the sets' order)
+    std::vector<uint64_t> cand;
+    for (auto& kv : groups)
+      if (kv.second == 8) cand.push_back(kv.first);
+    std::vector<char> ok(cand.size(), 1);
+    parallel_for(cand.size(), [&](size_t c0, size_t c1) {
+      for (size_t ci = c0; ci < c1; ++ci) {
+        const uint64_t key = cand[ci];
+        const int Lp = int(key >> 60);
+        const int pi = int((key >> 40) & 0xFFFFF), pj = int((key >> 20) & 0xFFFFF),
+                  pk = int(key & 0xFFFFF);
+        bool good = true;
+        for (int c = 0; c < 8 && good; ++c) {
+          const int b = find_leaf(g, Lp + 1, 2 * pi + (c & 1), 2 * pj + ((c >> 1) & 1),
+                                  2 * pk + ((c >> 2) & 1));
+          for (int dz = -1; dz <= 1 && good; ++dz)
+            for (int dy = -1; dy <= 1 && good; ++dy)
+              for (int dx = -1; dx <= 1 && good; ++dx) {
+                if (!dx && !dy && !dz) continue;
+                int id;
+                const int kind = neighbor_kind(g, b, dx, dy, dz, &id);
+                if (kind == 1) good = false;                           // finer neighbour
+                else if (kind == 0 && plan.refine[id]) good = false;   // refining neighbour
+              }
+        }
+        ok[ci] = good;
       }
-      if (ok) plan.parents.push_back({Lp, pi, pj, pk});
-    }
+    });
+    for (size_t ci = 0; ci < cand.size(); ++ci)
+      if (ok[ci]) {
+        const uint64_t key = cand[ci];
+        plan.parents.push_back({int(key >> 60), int((key >> 40) & 0xFFFFF),
+                                int((key >> 20) & 0xFFFFF), int(key & 0xFFFFF)});
+      }
   }
   plan.refined = 0;
   for (int b = 0; b < n; ++b) plan.refined += plan.refine[b];
@@ -1238,17 +1253,24 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
       const Key& k = g->leaves[b];
       if (coarsen_child.find(pack(k.L, k.i, k.j, k.k)) >= 0) slot[b] = nslot++;
     }
-    // kept blocks with a same-level neighbour in a coarsening sibling set
+    // kept blocks with a same-level neighbour in a coarsening sibling set,
+    // and the directions of those neighbours (host threads, one block each)
     std::vector<char> touches(n_old, 0);
-    for (int b = 0; b < n_old; ++b) {
-      if (slot[b] < 0) continue;
-      const Key& k = g->leaves[b];
-      for (int r = 0; r < 27; ++r) {
-        if (r == 13) continue;
-        const int id = find_leaf(g, k.L, k.i + r % 3 - 1, k.j + (r / 3) % 3 - 1, k.k + r / 9 - 1);
-        if (id >= 0 && slot[id] < 0) touches[id] = 1;
+    std::vector<int32_t> tdirs(n_old, 0);
+    parallel_for(size_t(n_old), [&](size_t b0, size_t b1) {
+      for (size_t b = b0; b < b1; ++b) {
+        if (slot[b] >= 0) continue;
+        const Key& k = g->leaves[b];
+        int32_t m = 0;
+        for (int r = 0; r < 27; ++r) {
+          if (r == 13) continue;
+          const int id = find_leaf(g, k.L, k.i + r % 3 - 1, k.j + (r / 3) % 3 - 1, k.k + r / 9 - 1);
+          if (id >= 0 && slot[id] >= 0) m |= 1 << r;
+        }
+        touches[b] = m != 0;
+        tdirs[b] = m;
       }
-    }
+    });
     // discarded details per slot: all of a child's; of a kept neighbour,
     // its coarse-extension slab toward the coarsening children (the update
     // of section 2.2.1 discards those too, up to the coarse region
@@ -1256,15 +1278,8 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
     std::vector<int32_t> dirs(nslot, kDiscardAll);
     for (int b = 0; b < n_old; ++b) {
       if (!touches[b]) continue;
-      const Key& k = g->leaves[b];
-      int32_t m = 0;
-      for (int r = 0; r < 27; ++r) {
-        if (r == 13) continue;
-        const int id = find_leaf(g, k.L, k.i + r % 3 - 1, k.j + (r / 3) % 3 - 1, k.k + r / 9 - 1);
-        if (id >= 0 && slot[id] >= 0 && dirs[slot[id]] == kDiscardAll) m |= 1 << r;
-      }
       slot[b] = nslot++;
-      dirs.push_back(m);
+      dirs.push_back(tdirs[b]);
     }
     const int H = Hreach(g->N, g->Nt);
     for (int b = 0; b < n_old; ++b) {
