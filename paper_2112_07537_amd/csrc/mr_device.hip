@@ -1646,8 +1646,9 @@ __global__ __launch_bounds__(256) void k_pass(DevGrid<T> g, const PItem* __restr
   const int n = sz[0] * sz[1] * sz[2];
   const int nb = g.nb;
   const int64_t nb3 = (int64_t)nb * nb * nb;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    int o[3] = {it.lo[0] + i % sz[0], it.lo[1] + (i / sz[0]) % sz[1], it.lo[2] + i / (sz[0] * sz[1])};
+  Iter3 qi(threadIdx.x, blockDim.x, sz[0], sz[1]);
+  for (int i = threadIdx.x; i < n; i += blockDim.x, qi.advance()) {
+    int o[3] = {it.lo[0] + qi.x, it.lo[1] + qi.y, it.lo[2] + qi.z};
     const int p = o[axis];
     int q[3] = {o[0], o[1], o[2]};
     double acc = 0.0;
