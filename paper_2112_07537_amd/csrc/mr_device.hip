@@ -1635,10 +1635,13 @@ __device__ __forceinline__ double pass_in(const DevGrid<T>& g, const PItem& it, 
   return io.det[(int64_t)s * nb * nb * nb + ((int64_t)gz * nb + gy) * nb + gx];
 }
 
-template <typename T, int N, int NT>
+// One instantiation per (filter, source): the unrolled taps of one filter
+// and one input path only, so that registers allow several workgroups per
+// CU.
+template <typename T, int N, int NT, int FILTER, int SRC>
 __global__ __launch_bounds__(256) void k_pass(DevGrid<T> g, const PItem* __restrict__ items,
-                                              int filter, int axis, int src_mode, int dst_mode,
-                                              PassIO<T> io) {
+                                              int axis, int dst_mode, PassIO<T> io) {
+  constexpr int filter = FILTER, src_mode = SRC;
   const PItem it = items[blockIdx.x];
   int sz[3];
 #pragma unroll
@@ -1656,7 +1659,7 @@ __global__ __launch_bounds__(256) void k_pass(DevGrid<T> g, const PItem* __restr
       q[axis] = c;
       acc += w * pass_in<T, N, NT>(g, it, src_mode, io, q[0], q[1], q[2]);
     };
-    if (filter == F_REFINE) {
+    if constexpr (filter == F_REFINE) {
       if ((p & 1) == 0) {
         tap(floordiv(p, 2), 1.0);
       } else {
@@ -1664,11 +1667,11 @@ __global__ __launch_bounds__(256) void k_pass(DevGrid<T> g, const PItem* __restr
 #pragma unroll
         for (int j = 0; j < N; ++j) tap(k + j + DD<N>::J0, DD<N>::w(j));
       }
-    } else if (filter == F_RESTRICT) {
+    } else if constexpr (filter == F_RESTRICT) {
 #pragma unroll
       for (int d = -Ha<N, NT>::R; d <= Ha<N, NT>::R; ++d)
         if (Ha<N, NT>::c(d) != 0.0) tap(2 * p + d, Ha<N, NT>::c(d));
-    } else if (filter == F_SYNTH) {
+    } else if constexpr (filter == F_SYNTH) {
       if ((p & 1) == 0) {
 #pragma unroll
         for (int d = -Js<N, NT>::R; d <= Js<N, NT>::R; ++d)
@@ -2110,8 +2113,21 @@ static void pass_t(const void* dgv, Wavelet w, int filter, int axis, int src_mod
                    const int32_t* slot, const uint32_t* tab, void* dst, hipStream_t s) {
   const DevGrid<T>& g = *static_cast<const DevGrid<T>*>(dgv);
   PassIO<T> io{din, dout, det, slot, tab, static_cast<T*>(dst)};
-  MR_WAVELET_SWITCH(w, hipLaunchKernelGGL((k_pass<T, N_, NT_>), dim3(n), dim3(256), 0, s, g, items,
-                                          filter, axis, src_mode, dst_mode, io));
+#define MR_PASS(F, S)                                                                    \
+  MR_WAVELET_SWITCH(w, hipLaunchKernelGGL((k_pass<T, N_, NT_, F, S>), dim3(n), dim3(256), 0, s, \
+                                          g, items, axis, dst_mode, io))
+  // the (filter, source) pairs the adaptation uses: each filter's first
+  // pass reads the field (refine, restrict) or the discarded details
+  // (synthesis), later passes the scratch box
+  if (filter == F_REFINE && src_mode == 0) MR_PASS(F_REFINE, 0);
+  else if (filter == F_REFINE) MR_PASS(F_REFINE, 1);
+  else if (filter == F_RESTRICT && src_mode == 0) MR_PASS(F_RESTRICT, 0);
+  else if (filter == F_RESTRICT) MR_PASS(F_RESTRICT, 1);
+  else if (filter == F_SYNTH && src_mode == 2) MR_PASS(F_SYNTH, 2);
+  else if (filter == F_SYNTH) MR_PASS(F_SYNTH, 1);
+  else if (src_mode == 0) MR_PASS(F_ANALYSIS, 0);
+  else MR_PASS(F_ANALYSIS, 1);
+#undef MR_PASS
 }
 void launch_pass(bool f32, const void* dgv, Wavelet w, int filter, int axis, int src_mode,
                  int dst_mode, const PItem* items, int n, const double* din, double* dout,
