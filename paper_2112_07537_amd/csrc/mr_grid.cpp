@@ -718,9 +718,11 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
         const int lo = it.lo[a], hi = it.hi[a];
         vol *= hi - lo;
         ev *= (hi - lo + (lo & 1 ? 0 : 1)) / 2;
-        int c = 0;
-        for (int v = lo - (N - 1); v < hi + (N - 1); ++v) c += (v >= lo && v < hi) || !(v & 1);
-        lat *= c;
+        // lattice along the axis: the even coordinates of [lo-N+1, hi+N-1)
+        // and the odd ones of [lo, hi)
+        const int s0 = lo - (N - 1), e0 = s0 + (s0 & 1), o0 = lo | 1;
+        const int nE = (hi + N - 1 - e0 + 1) >> 1, nO = hi > o0 ? (hi - o0 + 1) >> 1 : 0;
+        lat *= nE + nO;
       }
       L.sb_r += lat;
       L.sb_w += vol - ev;
@@ -745,20 +747,20 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
       const int q = std::min(it.hi[1] - it.lo[1], it.hi[2] - it.lo[2]);
       return q <= 3 ? 0 : (q <= 6 ? 1 : (q <= 12 ? 2 : 3));
     };
-    std::vector<RItem> sorted;
-    sorted.reserve(L.r.size());
-    for (int c = 0; c < 3; ++c) {
-      L.rcls[c] = int(sorted.size());
-      L.lds_rc[c] = 0;
-      for (const RItem& it : L.r)
-        if (cls(it) == c) {
-          sorted.push_back(it);
-          L.lds_rc[c] = std::max(L.lds_rc[c], rview_lds(it, H, esz));
-        }
+    std::vector<RItem> bucket[3];
+    L.lds_rc[0] = L.lds_rc[1] = L.lds_rc[2] = 0;
+    for (const RItem& it : L.r) {
+      const int c = cls(it);
+      if (c > 2) return fail(MR_EINVAL, "restriction item wider than 12 coarse points");
+      bucket[c].push_back(it);
+      L.lds_rc[c] = std::max(L.lds_rc[c], rview_lds(it, H, esz));
     }
-    L.rcls[3] = int(sorted.size());
-    if (sorted.size() != L.r.size()) return fail(MR_EINVAL, "restriction item wider than 12 coarse points");
-    L.r.swap(sorted);
+    L.r.clear();
+    for (int c = 0; c < 3; ++c) {
+      L.rcls[c] = int(L.r.size());
+      L.r.insert(L.r.end(), bucket[c].begin(), bucket[c].end());
+    }
+    L.rcls[3] = int(L.r.size());
   }
   const int lds_r = std::max(L.lds_rc[0], std::max(L.lds_rc[1], L.lds_rc[2]));
   if (L.lds_g > 64 * 1024 || lds_r > 64 * 1024 || L.lds_s > 64 * 1024)
