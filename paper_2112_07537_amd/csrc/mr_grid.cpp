@@ -690,6 +690,14 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
       if (cs > 32) return fail(MR_EINVAL, "refinement item too wide");
     }
   }
+  // a substitution item's lattice fits the kernel's per-axis tables (32)
+  for (const GItem& it : L.s)
+    for (int a = 0; a < 3; ++a) {
+      const int s0 = it.lo[a] - (N - 1), e0 = s0 + (s0 & 1), o0 = it.lo[a] | 1;
+      const int nE = (it.hi[a] + N - e0) >> 1;
+      const int nO = it.hi[a] > o0 ? (it.hi[a] - o0 + 1) >> 1 : 0;
+      if (nE + nO > 32) return fail(MR_EINVAL, "substitution item too wide");
+    }
   // algorithmic traffic of the lists (values per reconstruction)
   L.cf_w = L.cf_r = L.sb_w = L.sb_r = L.fc_w = L.fc_r = 0;
   for (const GItem& it : L.g) {
