@@ -1260,6 +1260,14 @@ __device__ __forceinline__ double lift_gamma(const double* w, int i) {
   return g;
 }
 
+// Smallest stride s >= nb (in 8-byte words) with step * s = nb (mod 16), or
+// nb when there is none below nb + 16.
+constexpr int y_row_stride(int nb, int step) {
+  for (int s = nb; s < nb + 16; ++s)
+    if ((step * s - nb) % 16 == 0) return s;
+  return nb;
+}
+
 // Smallest row stride >= v (in 4-byte words) for which 32 lanes reading
 // word r * stride + step * t (lane = r * per_row + t, t < per_row) hit 32
 // distinct LDS banks; v itself when no stride below v + 32 does.
@@ -1319,11 +1327,13 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
   //   XP values apart) on distinct banks (4-byte values), or continues the
   //   banks of the previous row (8-byte values, PH = NP mod 16); the odd
   //   half starts 16 banks after the even half;
-  // * x-pass rows of NBS doubles, 2 NBS = NB (mod 16), for the y pass.
+  // * x-pass rows of NBS doubles for the y pass, whose lanes take a row's NB
+  //   columns and then the same columns 2 YP rows further: 2 YP NBS = NB
+  //   (mod 16) makes the second row continue the first one's banks.
   constexpr int PH = sizeof(T) == 4 ? bank_free_stride((P + 1) / 2, XT, XP)
                                     : pad_to((P + 1) / 2, 16, NP % 16);
   constexpr int PS = sizeof(T) == 4 ? pad_to(P * PH, 32, 16) : pad_to(P * PH, 16, 8);
-  constexpr int NBS = pad_to(NB, 8, (NB % 16) / 2);
+  constexpr int NBS = y_row_stride(NB, 2 * YP);
   __shared__ __align__(16) T pl[ZG][2 * PS];   // input planes: even, odd columns
   __shared__ double t1[ZG][P * NBS];  // after the x pass
   __shared__ double t2[ZG][NB * NB];  // after the y pass
