@@ -672,104 +672,144 @@ static mr_status build_lists(mr_grid* g, int D, Lists& L) {
       for (int b = lo; b < hi && parts[c].ok; ++b) parts[c].ok = one_block(b, parts[c]);
     }
   });
-  for (Part& P : parts) {
-    if (!P.ok) return fail(MR_EINVAL, "finer region not covered by level+1 leaves");
-    L.g.insert(L.g.end(), P.g.begin(), P.g.end());
-    L.s.insert(L.s.end(), P.s.begin(), P.s.end());
-    L.r.insert(L.r.end(), P.r.begin(), P.r.end());
-    L.out_points += P.pts;
-  }
-  // sample boxes of c->f and substitution items must stay inside the map,
-  // and their extent fits the kernel's per-axis cell table (32 samples)
-  for (const GItem& it : L.g) {
-    for (int a = 0; a < 3; ++a) {
-      int clo, cs;
-      gview_samples(it.lo[a], it.hi[a], N, &clo, &cs);
-      if (2 * clo < -nb / 2 || 2 * (clo + cs - 1) >= 3 * nb / 2)
-        return fail(MR_EINVAL, "refinement samples leave the owner map");
-      if (cs > 32) return fail(MR_EINVAL, "refinement item too wide");
-    }
-  }
-  // a substitution item's lattice fits the kernel's per-axis tables (32)
-  for (const GItem& it : L.s)
-    for (int a = 0; a < 3; ++a) {
-      const int s0 = it.lo[a] - (N - 1), e0 = s0 + (s0 & 1), o0 = it.lo[a] | 1;
-      const int nE = (it.hi[a] + N - e0) >> 1;
-      const int nO = it.hi[a] > o0 ? (it.hi[a] - o0 + 1) >> 1 : 0;
-      if (nE + nO > 32) return fail(MR_EINVAL, "substitution item too wide");
-    }
-  // algorithmic traffic of the lists (values per reconstruction)
-  L.cf_w = L.cf_r = L.sb_w = L.sb_r = L.fc_w = L.fc_r = 0;
-  for (const GItem& it : L.g) {
-    int64_t r = 1;
-    for (int a = 0; a < 3; ++a) {
-      int clo, cs;
-      gview_samples(it.lo[a], it.hi[a], N, &clo, &cs);
-      r *= cs;
-    }
-    L.cf_r += r;
-    for (int rr = 0; rr < 27; ++rr) {
-      if (!((it.rmask >> rr) & 1)) continue;
-      int blo[3], bhi[3];
-      region_box(nb, Dc, rr, blo, bhi);
-      int64_t v = 1;
-      for (int a = 0; a < 3; ++a) v *= std::max(0, std::min(bhi[a], it.hi[a]) - std::max(blo[a], it.lo[a]));
-      L.cf_w += v;
-    }
-  }
-  {
-    // slab points (every point of the item boxes but the all-even ones) and
-    // staged lattice points per item
-    for (const GItem& it : L.s) {
-      int64_t vol = 1, ev = 1, lat = 1;
-      for (int a = 0; a < 3; ++a) {
-        const int lo = it.lo[a], hi = it.hi[a];
-        vol *= hi - lo;
-        ev *= (hi - lo + (lo & 1 ? 0 : 1)) / 2;
-        // lattice along the axis: the even coordinates of [lo-N+1, hi+N-1)
-        // and the odd ones of [lo, hi)
-        const int s0 = lo - (N - 1), e0 = s0 + (s0 & 1), o0 = lo | 1;
-        const int nE = (hi + N - 1 - e0 + 1) >> 1, nO = hi > o0 ? (hi - o0 + 1) >> 1 : 0;
-        lat *= nE + nO;
+  // per part on the host threads: item checks, algorithmic traffic, LDS
+  // maxima, and the restriction items split by column-length class
+  auto cls = [](const RItem& it) {
+    const int q = std::min(it.hi[1] - it.lo[1], it.hi[2] - it.lo[2]);
+    return q <= 3 ? 0 : (q <= 6 ? 1 : (q <= 12 ? 2 : 3));
+  };
+  struct Post {
+    int err = 0;   // 1 samples leave the map, 2 c->f too wide, 3 substitution too wide, 4 restriction too wide
+    int64_t cf_w = 0, cf_r = 0, sb_w = 0, sb_r = 0, fc_w = 0, fc_r = 0;
+    int lds_g = 0, lds_s = 0, lds_rc[3] = {0, 0, 0};
+    std::vector<RItem> rc[3];
+  };
+  std::vector<Post> post(parts.size());
+  parallel_for(parts.size(), [&](size_t c0, size_t c1) {
+    for (size_t c = c0; c < c1; ++c) {
+      const Part& P = parts[c];
+      Post& Q = post[c];
+      if (!P.ok) continue;
+      // sample boxes of c->f items stay inside the owner map and fit the
+      // kernel's per-axis cell table (32 samples)
+      for (const GItem& it : P.g) {
+        int64_t r = 1;
+        for (int a = 0; a < 3; ++a) {
+          int clo, cs;
+          gview_samples(it.lo[a], it.hi[a], N, &clo, &cs);
+          if (2 * clo < -nb / 2 || 2 * (clo + cs - 1) >= 3 * nb / 2) Q.err = Q.err ? Q.err : 1;
+          if (cs > 32) Q.err = Q.err ? Q.err : 2;
+          r *= cs;
+        }
+        Q.cf_r += r;
+        for (int rr = 0; rr < 27; ++rr) {
+          if (!((it.rmask >> rr) & 1)) continue;
+          int blo[3], bhi[3];
+          region_box(nb, Dc, rr, blo, bhi);
+          int64_t v = 1;
+          for (int a = 0; a < 3; ++a)
+            v *= std::max(0, std::min(bhi[a], it.hi[a]) - std::max(blo[a], it.lo[a]));
+          Q.cf_w += v;
+        }
+        Q.lds_g = std::max(Q.lds_g, gview_lds(it, N, esz));
       }
-      L.sb_r += lat;
-      L.sb_w += vol - ev;
+      // substitution items: slab points (every point of the box but the
+      // all-even ones) and staged lattice points (per axis the even
+      // coordinates of [lo-N+1, hi+N-1) and the odd ones of [lo, hi), at
+      // most 32, the kernel's per-axis tables)
+      for (const GItem& it : P.s) {
+        int64_t vol = 1, ev = 1, lat = 1;
+        for (int a = 0; a < 3; ++a) {
+          const int lo = it.lo[a], hi = it.hi[a];
+          vol *= hi - lo;
+          ev *= (hi - lo + (lo & 1 ? 0 : 1)) / 2;
+          const int s0 = lo - (N - 1), e0 = s0 + (s0 & 1), o0 = lo | 1;
+          const int nE = (hi + N - e0) >> 1, nO = hi > o0 ? (hi - o0 + 1) >> 1 : 0;
+          if (nE + nO > 32) Q.err = Q.err ? Q.err : 3;
+          lat *= nE + nO;
+        }
+        Q.sb_r += lat;
+        Q.sb_w += vol - ev;
+        Q.lds_s = std::max(Q.lds_s, subst_lds(it, N, esz));
+      }
+      for (const RItem& it : P.r) {
+        int64_t w = 1, r = 1;
+        for (int a = 0; a < 3; ++a) {
+          const int q = it.hi[a] - it.lo[a];
+          w *= q;
+          r *= 2 * (q - 1) + 1 + 2 * H;
+        }
+        Q.fc_w += w;
+        Q.fc_r += r;
+        const int k = cls(it);
+        if (k > 2) {
+          Q.err = Q.err ? Q.err : 4;
+          continue;
+        }
+        Q.rc[k].push_back(it);
+        Q.lds_rc[k] = std::max(Q.lds_rc[k], rview_lds(it, H, esz));
+      }
     }
-  }
-  for (const RItem& it : L.r) {
-    int64_t w = 1, r = 1;
-    for (int a = 0; a < 3; ++a) {
-      const int q = it.hi[a] - it.lo[a];
-      w *= q;
-      r *= 2 * (q - 1) + 1 + 2 * H;
+  });
+  static const char* kPostErr[5] = {"", "refinement samples leave the owner map",
+                                    "refinement item too wide", "substitution item too wide",
+                                    "restriction item wider than 12 coarse points"};
+  size_t ng = 0, ns = 0, nr[3] = {0, 0, 0};
+  L.cf_w = L.cf_r = L.sb_w = L.sb_r = L.fc_w = L.fc_r = 0;
+  L.lds_g = L.lds_s = 0;
+  L.lds_rc[0] = L.lds_rc[1] = L.lds_rc[2] = 0;
+  for (size_t c = 0; c < parts.size(); ++c) {
+    if (!parts[c].ok) return fail(MR_EINVAL, "finer region not covered by level+1 leaves");
+    const Post& Q = post[c];
+    if (Q.err) return fail(MR_EINVAL, kPostErr[Q.err]);
+    ng += parts[c].g.size();
+    ns += parts[c].s.size();
+    for (int k = 0; k < 3; ++k) {
+      nr[k] += Q.rc[k].size();
+      L.lds_rc[k] = std::max(L.lds_rc[k], Q.lds_rc[k]);
     }
-    L.fc_w += w;
-    L.fc_r += r;
+    L.cf_w += Q.cf_w;
+    L.cf_r += Q.cf_r;
+    L.sb_w += Q.sb_w;
+    L.sb_r += Q.sb_r;
+    L.fc_w += Q.fc_w;
+    L.fc_r += Q.fc_r;
+    L.lds_g = std::max(L.lds_g, Q.lds_g);
+    L.lds_s = std::max(L.lds_s, Q.lds_s);
+    L.out_points += parts[c].pts;
   }
-  L.lds_g = 0;
-  for (const GItem& it : L.g) L.lds_g = std::max(L.lds_g, gview_lds(it, N, esz));
-  L.lds_s = 0;
-  for (const GItem& it : L.s) L.lds_s = std::max(L.lds_s, subst_lds(it, N, esz));
+  // concatenation in part order (restriction items by class, then part),
+  // copied on the host threads
+  L.rcls[0] = 0;
+  L.rcls[1] = int(nr[0]);
+  L.rcls[2] = int(nr[0] + nr[1]);
+  L.rcls[3] = int(nr[0] + nr[1] + nr[2]);
+  L.g.resize(ng);
+  L.s.resize(ns);
+  L.r.resize(size_t(L.rcls[3]));
+  std::vector<size_t> og(parts.size()), os(parts.size()), orr[3];
+  for (int k = 0; k < 3; ++k) orr[k].resize(parts.size());
   {
-    auto cls = [](const RItem& it) {
-      const int q = std::min(it.hi[1] - it.lo[1], it.hi[2] - it.lo[2]);
-      return q <= 3 ? 0 : (q <= 6 ? 1 : (q <= 12 ? 2 : 3));
-    };
-    std::vector<RItem> bucket[3];
-    L.lds_rc[0] = L.lds_rc[1] = L.lds_rc[2] = 0;
-    for (const RItem& it : L.r) {
-      const int c = cls(it);
-      if (c > 2) return fail(MR_EINVAL, "restriction item wider than 12 coarse points");
-      bucket[c].push_back(it);
-      L.lds_rc[c] = std::max(L.lds_rc[c], rview_lds(it, H, esz));
+    size_t a = 0, b = 0, r[3] = {0, 0, 0};
+    for (size_t c = 0; c < parts.size(); ++c) {
+      og[c] = a;
+      os[c] = b;
+      a += parts[c].g.size();
+      b += parts[c].s.size();
+      for (int k = 0; k < 3; ++k) {
+        orr[k][c] = size_t(L.rcls[k]) + r[k];
+        r[k] += post[c].rc[k].size();
+      }
     }
-    L.r.clear();
-    for (int c = 0; c < 3; ++c) {
-      L.rcls[c] = int(L.r.size());
-      L.r.insert(L.r.end(), bucket[c].begin(), bucket[c].end());
-    }
-    L.rcls[3] = int(L.r.size());
   }
+  parallel_for(parts.size(), [&](size_t c0, size_t c1) {
+    for (size_t c = c0; c < c1; ++c) {
+      std::copy(parts[c].g.begin(), parts[c].g.end(), L.g.begin() + og[c]);
+      std::copy(parts[c].s.begin(), parts[c].s.end(), L.s.begin() + os[c]);
+      for (int k = 0; k < 3; ++k)
+        std::copy(post[c].rc[k].begin(), post[c].rc[k].end(), L.r.begin() + orr[k][c]);
+    }
+  });
   const int lds_r = std::max(L.lds_rc[0], std::max(L.lds_rc[1], L.lds_rc[2]));
   if (L.lds_g > 64 * 1024 || lds_r > 64 * 1024 || L.lds_s > 64 * 1024)
     return fail(MR_EINVAL, "ghost work item exceeds LDS");
