@@ -1291,11 +1291,6 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
     std::vector<int32_t> pairs;
     std::vector<PItem> ref[3], crs[3], upd[3];
     int64_t scr = 0;
-    auto add3 = [&](std::vector<PItem>* v, PItem p0, PItem p1, PItem p2) {
-      v[0].push_back(p0);
-      v[1].push_back(p1);
-      v[2].push_back(p2);
-    };
     // slots of coarsening children for their detail arrays
     std::vector<int32_t> slot(n_old, -1);
     int nslot = 0;
@@ -1332,100 +1327,174 @@ static mr_status apply_plan(mr_grid* g, const Plan& plan, std::unordered_set<uin
       dirs.push_back(tdirs[b]);
     }
     const int H = Hreach(g->N, g->Nt);
-    for (int b = 0; b < n_old; ++b) {
-      const Key& k = g->leaves[b];
-      const uint64_t key = pack(k.L, k.i, k.j, k.k);
-      if (plan.refine[b]) {
-        for (int c = 0; c < 8; ++c) {
-          const int o[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
-          const int child = nidx.find(pack(k.L + 1, 2 * k.i + o[0], 2 * k.j + o[1], 2 * k.k + o[2]));
-          int flo[3], fhi[3], clo[3], chi[3];
-          for (int a = 0; a < 3; ++a) {
-            flo[a] = o[a] * nb;
-            fhi[a] = flo[a] + nb;
-            clo[a] = o[a] * nb / 2 - g->N / 2;
-            chi[a] = o[a] * nb / 2 + nb / 2 + g->N / 2;
+    // item sets in block order: 8 refinement sets per refined block, one
+    // coarsening set per coarsening child, one copy pair and possibly one
+    // update set per kept block; each set takes two scratch boxes of fixed
+    // size.  Counted, then written, per contiguous chunk of blocks on host
+    // threads, with offsets and scratch in block order.
+    const int hb2 = nb / 2;
+    const int Rup = std::max(g->Nt ? 1 : 0, g->Nt ? g->N : g->N - 1);
+    const int64_t ref_sc = int64_t(nb) * (hb2 + g->N) * (hb2 + g->N) + int64_t(nb) * nb * (hb2 + g->N);
+    const int64_t crs_sc = int64_t(hb2) * (nb - 1 + 2 * H) * (nb - 1 + 2 * H) +
+                           int64_t(hb2) * hb2 * (nb - 1 + 2 * H);
+    const int64_t upd_sc = int64_t(nb + 2 * Rup) * (nb + 2 * Rup) * nb + int64_t(nb + 2 * Rup) * nb * nb;
+    const int nch = std::max(1, std::min(64, n_old / 256));
+    struct Cnt {
+      size_t ref = 0, crs = 0, upd = 0, pairs = 0;
+      int64_t sc = 0;
+    };
+    std::vector<Cnt> cnt(nch + 1);
+    auto chunk_lo = [&](size_t c) { return int(int64_t(n_old) * int64_t(c) / nch); };
+    parallel_for(size_t(nch), [&](size_t c0, size_t c1) {
+      for (size_t c = c0; c < c1; ++c) {
+        Cnt& C = cnt[c + 1];
+        for (int b = chunk_lo(c); b < chunk_lo(c + 1); ++b) {
+          const Key& k = g->leaves[b];
+          if (plan.refine[b]) {
+            C.ref += 8;
+            C.sc += 8 * ref_sc;
+          } else if (coarsen_child.find(pack(k.L, k.i, k.j, k.k)) >= 0) {
+            C.crs += 1;
+            C.sc += crs_sc;
+          } else {
+            C.pairs += 1;
+            if (touches[b]) {
+              C.upd += 1;
+              C.sc += upd_sc;
+            }
           }
-          PItem p0{}, p1{}, p2{};
-          p0.src_blk = p1.src_blk = p2.src_blk = b;
-          p0.dst_blk = p1.dst_blk = p2.dst_blk = child;
-          const int b0lo[3] = {flo[0], clo[1], clo[2]}, b0hi[3] = {fhi[0], chi[1], chi[2]};
-          const int b1lo[3] = {flo[0], flo[1], clo[2]}, b1hi[3] = {fhi[0], fhi[1], chi[2]};
-          for (int a = 0; a < 3; ++a) {
-            p0.lo[a] = b0lo[a]; p0.hi[a] = b0hi[a];
-            p1.lo[a] = b1lo[a]; p1.hi[a] = b1hi[a];
-            p1.ilo[a] = b0lo[a]; p1.isz[a] = b0hi[a] - b0lo[a];
-            p2.lo[a] = flo[a]; p2.hi[a] = fhi[a];
-            p2.ilo[a] = b1lo[a]; p2.isz[a] = b1hi[a] - b1lo[a];
-            p2.dlo[a] = flo[a];
-          }
-          p0.out_off = scr;
-          p1.in_off = scr;
-          scr += box_size(b0lo, b0hi);
-          p1.out_off = scr;
-          p2.in_off = scr;
-          scr += box_size(b1lo, b1hi);
-          add3(ref, p0, p1, p2);
-        }
-      } else if (coarsen_child.find(key) >= 0) {
-        const int o[3] = {k.i & 1, k.j & 1, k.k & 1};
-        const int parent = nidx.find(pack(k.L - 1, k.i >> 1, k.j >> 1, k.k >> 1));
-        const int hb = nb / 2;
-        const int b0lo[3] = {0, -H, -H}, b0hi[3] = {hb, nb - 1 + H, nb - 1 + H};
-        const int b1lo[3] = {0, 0, -H}, b1hi[3] = {hb, hb, nb - 1 + H};
-        const int b2lo[3] = {0, 0, 0}, b2hi[3] = {hb, hb, hb};
-        PItem p0{}, p1{}, p2{};
-        p0.src_blk = p1.src_blk = p2.src_blk = b;
-        p0.dst_blk = p1.dst_blk = p2.dst_blk = parent;
-        for (int a = 0; a < 3; ++a) {
-          p0.lo[a] = b0lo[a]; p0.hi[a] = b0hi[a];
-          p1.lo[a] = b1lo[a]; p1.hi[a] = b1hi[a];
-          p1.ilo[a] = b0lo[a]; p1.isz[a] = b0hi[a] - b0lo[a];
-          p2.lo[a] = b2lo[a]; p2.hi[a] = b2hi[a];
-          p2.ilo[a] = b1lo[a]; p2.isz[a] = b1hi[a] - b1lo[a];
-          p2.dlo[a] = -o[a] * hb;
-        }
-        p0.out_off = scr;
-        p1.in_off = scr;
-        scr += box_size(b0lo, b0hi);
-        p1.out_off = scr;
-        p2.in_off = scr;
-        scr += box_size(b1lo, b1hi);
-        add3(crs, p0, p1, p2);
-      } else {
-        const int nid = nidx.find(key);
-        pairs.push_back(nid);
-        pairs.push_back(b);
-        // update step on kept blocks next to a coarsening sibling set of
-        // their own level (Table 3, update after neighbour has coarsened)
-        if (touches[b]) {
-          int r = 0;
-          const int Jr = g->Nt ? 1 : 0, Kr = g->Nt ? g->N : g->N - 1;
-          r = std::max(Jr, Kr);
-          const int b0lo[3] = {-r, -r, 0}, b0hi[3] = {nb + r, nb + r, nb};
-          const int b1lo[3] = {-r, 0, 0}, b1hi[3] = {nb + r, nb, nb};
-          const int b2lo[3] = {0, 0, 0}, b2hi[3] = {nb, nb, nb};
-          PItem p0{}, p1{}, p2{};
-          p0.src_blk = p1.src_blk = p2.src_blk = b;
-          p0.dst_blk = p1.dst_blk = p2.dst_blk = nid;
-          for (int a = 0; a < 3; ++a) {
-            p0.lo[a] = b0lo[a]; p0.hi[a] = b0hi[a];
-            p1.lo[a] = b1lo[a]; p1.hi[a] = b1hi[a];
-            p1.ilo[a] = b0lo[a]; p1.isz[a] = b0hi[a] - b0lo[a];
-            p2.lo[a] = b2lo[a]; p2.hi[a] = b2hi[a];
-            p2.ilo[a] = b1lo[a]; p2.isz[a] = b1hi[a] - b1lo[a];
-            p2.dlo[a] = 0;
-          }
-          p0.out_off = scr;
-          p1.in_off = scr;
-          scr += box_size(b0lo, b0hi);
-          p1.out_off = scr;
-          p2.in_off = scr;
-          scr += box_size(b1lo, b1hi);
-          add3(upd, p0, p1, p2);
         }
       }
+    });
+    for (int c = 0; c < nch; ++c) {
+      cnt[c + 1].ref += cnt[c].ref;
+      cnt[c + 1].crs += cnt[c].crs;
+      cnt[c + 1].upd += cnt[c].upd;
+      cnt[c + 1].pairs += cnt[c].pairs;
+      cnt[c + 1].sc += cnt[c].sc;
     }
+    for (int p = 0; p < 3; ++p) {
+      ref[p].resize(cnt[nch].ref);
+      crs[p].resize(cnt[nch].crs);
+      upd[p].resize(cnt[nch].upd);
+    }
+    pairs.resize(2 * cnt[nch].pairs);
+    scr = cnt[nch].sc;
+    std::vector<char> layout_ok(nch, 1);
+    parallel_for(size_t(nch), [&](size_t c0, size_t c1) {
+      for (size_t ch = c0; ch < c1; ++ch) {
+        size_t ir = cnt[ch].ref, ic = cnt[ch].crs, iu = cnt[ch].upd, ip = cnt[ch].pairs;
+        int64_t sc = cnt[ch].sc;
+        const int blo = chunk_lo(ch), bhi = chunk_lo(ch + 1);
+        for (int b = blo; b < bhi; ++b) {
+          const Key& k = g->leaves[b];
+          const uint64_t key = pack(k.L, k.i, k.j, k.k);
+          if (plan.refine[b]) {
+            for (int c = 0; c < 8; ++c) {
+              const int o[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+              const int child = nidx.find(pack(k.L + 1, 2 * k.i + o[0], 2 * k.j + o[1], 2 * k.k + o[2]));
+              int flo[3], fhi[3], clo[3], chi[3];
+              for (int a = 0; a < 3; ++a) {
+                flo[a] = o[a] * nb;
+                fhi[a] = flo[a] + nb;
+                clo[a] = o[a] * nb / 2 - g->N / 2;
+                chi[a] = o[a] * nb / 2 + nb / 2 + g->N / 2;
+              }
+              PItem p0{}, p1{}, p2{};
+              p0.src_blk = p1.src_blk = p2.src_blk = b;
+              p0.dst_blk = p1.dst_blk = p2.dst_blk = child;
+              const int b0lo[3] = {flo[0], clo[1], clo[2]}, b0hi[3] = {fhi[0], chi[1], chi[2]};
+              const int b1lo[3] = {flo[0], flo[1], clo[2]}, b1hi[3] = {fhi[0], fhi[1], chi[2]};
+              for (int a = 0; a < 3; ++a) {
+                p0.lo[a] = b0lo[a]; p0.hi[a] = b0hi[a];
+                p1.lo[a] = b1lo[a]; p1.hi[a] = b1hi[a];
+                p1.ilo[a] = b0lo[a]; p1.isz[a] = b0hi[a] - b0lo[a];
+                p2.lo[a] = flo[a]; p2.hi[a] = fhi[a];
+                p2.ilo[a] = b1lo[a]; p2.isz[a] = b1hi[a] - b1lo[a];
+                p2.dlo[a] = flo[a];
+              }
+              p0.out_off = sc;
+              p1.in_off = sc;
+              sc += box_size(b0lo, b0hi);
+              p1.out_off = sc;
+              p2.in_off = sc;
+              sc += box_size(b1lo, b1hi);
+              ref[0][ir] = p0;
+              ref[1][ir] = p1;
+              ref[2][ir] = p2;
+              ++ir;
+            }
+          } else if (coarsen_child.find(key) >= 0) {
+            const int o[3] = {k.i & 1, k.j & 1, k.k & 1};
+            const int parent = nidx.find(pack(k.L - 1, k.i >> 1, k.j >> 1, k.k >> 1));
+            const int hb = nb / 2;
+            const int b0lo[3] = {0, -H, -H}, b0hi[3] = {hb, nb - 1 + H, nb - 1 + H};
+            const int b1lo[3] = {0, 0, -H}, b1hi[3] = {hb, hb, nb - 1 + H};
+            const int b2lo[3] = {0, 0, 0}, b2hi[3] = {hb, hb, hb};
+            PItem p0{}, p1{}, p2{};
+            p0.src_blk = p1.src_blk = p2.src_blk = b;
+            p0.dst_blk = p1.dst_blk = p2.dst_blk = parent;
+            for (int a = 0; a < 3; ++a) {
+              p0.lo[a] = b0lo[a]; p0.hi[a] = b0hi[a];
+              p1.lo[a] = b1lo[a]; p1.hi[a] = b1hi[a];
+              p1.ilo[a] = b0lo[a]; p1.isz[a] = b0hi[a] - b0lo[a];
+              p2.lo[a] = b2lo[a]; p2.hi[a] = b2hi[a];
+              p2.ilo[a] = b1lo[a]; p2.isz[a] = b1hi[a] - b1lo[a];
+              p2.dlo[a] = -o[a] * hb;
+            }
+            p0.out_off = sc;
+            p1.in_off = sc;
+            sc += box_size(b0lo, b0hi);
+            p1.out_off = sc;
+            p2.in_off = sc;
+            sc += box_size(b1lo, b1hi);
+            crs[0][ic] = p0;
+            crs[1][ic] = p1;
+            crs[2][ic] = p2;
+            ++ic;
+          } else {
+            const int nid = nidx.find(key);
+            pairs[2 * ip] = nid;
+            pairs[2 * ip + 1] = b;
+            ++ip;
+            // update step on kept blocks next to a coarsening sibling set of
+            // their own level (Table 3, update after neighbour has coarsened)
+            if (touches[b]) {
+              int r = 0;
+              const int Jr = g->Nt ? 1 : 0, Kr = g->Nt ? g->N : g->N - 1;
+              r = std::max(Jr, Kr);
+              const int b0lo[3] = {-r, -r, 0}, b0hi[3] = {nb + r, nb + r, nb};
+              const int b1lo[3] = {-r, 0, 0}, b1hi[3] = {nb + r, nb, nb};
+              const int b2lo[3] = {0, 0, 0}, b2hi[3] = {nb, nb, nb};
+              PItem p0{}, p1{}, p2{};
+              p0.src_blk = p1.src_blk = p2.src_blk = b;
+              p0.dst_blk = p1.dst_blk = p2.dst_blk = nid;
+              for (int a = 0; a < 3; ++a) {
+                p0.lo[a] = b0lo[a]; p0.hi[a] = b0hi[a];
+                p1.lo[a] = b1lo[a]; p1.hi[a] = b1hi[a];
+                p1.ilo[a] = b0lo[a]; p1.isz[a] = b0hi[a] - b0lo[a];
+                p2.lo[a] = b2lo[a]; p2.hi[a] = b2hi[a];
+                p2.ilo[a] = b1lo[a]; p2.isz[a] = b1hi[a] - b1lo[a];
+                p2.dlo[a] = 0;
+              }
+              p0.out_off = sc;
+              p1.in_off = sc;
+              sc += box_size(b0lo, b0hi);
+              p1.out_off = sc;
+              p2.in_off = sc;
+              sc += box_size(b1lo, b1hi);
+              upd[0][iu] = p0;
+              upd[1][iu] = p1;
+              upd[2][iu] = p2;
+              ++iu;
+            }
+          }
+        }
+        if (sc != cnt[ch + 1].sc) layout_ok[ch] = 0;
+      }
+    });
+    for (int c = 0; c < nch; ++c)
+      if (!layout_ok[c]) return fail(MR_EINVAL, "adaptation scratch layout does not add up");
     // grow-only buffers kept by the grid (no allocation per adaptation)
     DevBuf& d_pairs = g->ad_pairs;
     DevBuf& d_items = g->ad_items;
