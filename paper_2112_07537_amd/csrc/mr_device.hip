@@ -1343,11 +1343,14 @@ __global__ __launch_bounds__(NB* NB) void k_details(DevGrid<T> g, int ef, int eb
   // then sits in the same XCD's L2
   const int b = first + xcd_item(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
+  const int slot = __builtin_amdgcn_readfirstlane(det_slot ? det_slot[b] : -1);
+  // a pass for the discarded details (det_out given) needs only the blocks
+  // with a slot; the others leave at once (the whole workgroup)
+  if (det_out && slot < 0) return;
   if (tid < 27) make_desc(g, b, tid, desc[tid]);
   if (tid == 0) nonfinite = 0;
   __syncthreads();
   const int tx = tid % NB, ty = tid / NB;
-  const int slot = __builtin_amdgcn_readfirstlane(det_slot ? det_slot[b] : -1);
   const T* fbuf = g.field;
   const T* pbuf = g.patch;
   // Each thread loads the same LPT positions (x, y) of every input plane

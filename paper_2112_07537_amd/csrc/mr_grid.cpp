@@ -1108,7 +1108,9 @@ static void details_pass(mr_grid* g, void* field, const int32_t* det_slot, doubl
     launch_details(g->f32, v.raw, w, g->Ef, g->Eb, bands, det_slot, det_out, 0, n, strm);
   }
   prof_end(g, 1, a, e, !plain, int64_t(n) * g->nb * g->nb * g->nb);
-  launch_combine(v.raw, bands, g->cfg.detail_ext, norms, n, strm);
+  // a pass for the discarded details of an adaptation visits only the
+  // blocks with a slot and leaves the norms alone
+  if (!det_out) launch_combine(v.raw, bands, g->cfg.detail_ext, norms, n, strm);
 }
 
 static mr_status check_err(mr_grid* g) {
