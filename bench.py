@@ -476,7 +476,18 @@ def main():
                                "detail pass; 9 words per point",
                      "bytes_per_step": step_bytes,
                      "dominant_kernel": dom[0],
-                     "dominant_kernel_ms_per_step": dom[1]["ms_per_step"] if dom[1] else None},
+                     "dominant_kernel_ms_per_step": dom[1]["ms_per_step"] if dom[1] else None,
+                     # the same roofline for the dominant kernel alone: its
+                     # algorithmic bytes per launch over its average launch
+                     # duration (HIP events on the grid's stream); traffic
+                     # from the counter summary when it matches the source
+                     "dominant": None if not dom[1] else {
+                         "kernel": dom[0], "bound": "hbm",
+                         "avg_launch_ms": dom[1]["avg_launch_ms"],
+                         "bytes_per_launch": dom[1]["bytes_per_step"] / dom[1]["launches_per_step"],
+                         "achieved": dom[1]["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": dom[1]["frac"],
+                         "traffic": (traffic["per_launch"].get(dom[0]) if traffic else None)}},
         "kernels": kernels,
         "tuning": tuning,
         "instrumented_ms_per_step": ms_instr,
